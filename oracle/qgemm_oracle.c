@@ -1,0 +1,243 @@
+/*
+ * qgemm_oracle.c -- plain, slow, obviously correct CPU reference for quaternion
+ * matrix multiplication.  TEST INFRASTRUCTURE ONLY: it is called by the test
+ * suite, by the smoke check and by the CPU-baseline leg of the benchmark, and
+ * never by the product path.  It shares no code, header, table or constant
+ * with the GPU library.
+ *
+ * Everything is IEEE binary64.  Inputs stored in binary32 are widened exactly
+ * by the caller before they reach this file.
+ *
+ * Notation follows Williams-Young & Li, "On the Efficacy and High-Performance
+ * Implementation of Quaternion Matrix Multiplication":
+ *   - a quaternion is q = q0 e0 + q1 e1 + q2 e2 + q3 e3, stored as the four
+ *     contiguous reals [q0, q1, q2, q3]                     (Sec. 2.1, Eq. quaternion_def;
+ *                                                          storage: Sec. 4)
+ *   - the product is the Hamilton product                   (Sec. 2.1, Eq. quaternion_prod)
+ *   - the conjugate negates the vector part                 (Sec. 2.1, Eq. quaternion_conj)
+ *   - (Q^H)_{mu nu} = conj(Q_{nu mu}), Q^T plain transpose  (Sec. 2.2; notation section)
+ *   - matrices are column-major                             (Sec. 3.1, Eq. general_gemm)
+ *   - left scalar times a product: (qPQ)_{mu nu} = q * sum_k P_{mu k} Q_{k nu}
+ *                                                          (Sec. 2.2, left scalar products)
+ *   - GEMM: C = alpha A B + beta C, alpha and beta on the left
+ *                                                          (Sec. 3.1, Eq. general_gemm; Alg. 1)
+ *
+ * op codes: 0 = N (as stored), 1 = T (transpose, no conjugation),
+ *           2 = C (conjugate transpose), 3 = R (conjugate, no transpose).
+ * The T/C reading of op() and the R op used by the gradient are readings of
+ * this build, not the paper's (the paper defines only ^T and ^H on matrices).
+ *
+ * Parity pins for every function live in tests/test_oracle_pins.py.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads the oracle uses (<= 0: leave the runtime default). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* Threads a parallel region of the oracle would use now. */
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Hamilton product out = p q, written out term by term from Eq. quaternion_prod:
+ *   scalar part : p0 q0 - sum_{i=1..3} p_i q_i
+ *   vector part k: p0 q_k + p_k q0 + sum_{i,j} eps_{ijk} p_i q_j
+ * with the Levi-Civita symbol eps_{123} = +1 (so e1 e2 = e3, Eq. quaternion_alg).
+ * The eps sum for k = 1 is p2 q3 - p3 q2, for k = 2 is p3 q1 - p1 q3, for k = 3
+ * is p1 q2 - p2 q1.  out may alias neither p nor q. */
+void oracle_hamilton(const double *p, const double *q, double *out)
+{
+    out[0] = p[0] * q[0] - (p[1] * q[1] + p[2] * q[2] + p[3] * q[3]);
+    out[1] = p[0] * q[1] + p[1] * q[0] + (p[2] * q[3] - p[3] * q[2]);
+    out[2] = p[0] * q[2] + p[2] * q[0] + (p[3] * q[1] - p[1] * q[3]);
+    out[3] = p[0] * q[3] + p[3] * q[0] + (p[1] * q[2] - p[2] * q[1]);
+}
+
+/* Quaternion conjugate, Eq. quaternion_conj. */
+static void conj_q(const double *q, double *out)
+{
+    out[0] = q[0];
+    out[1] = -q[1];
+    out[2] = -q[2];
+    out[3] = -q[3];
+}
+
+/* Materialise op(X) as a dense rows x cols column-major quaternion matrix
+ * (leading dimension = rows).  X is the stored matrix with leading dimension
+ * ldx; for op N/R it is rows x cols, for op T/C it is cols x rows. */
+static double *materialise_op(int op, int64_t rows, int64_t cols,
+                              const double *X, int64_t ldx)
+{
+    double *Y = (double *)malloc(sizeof(double) * 4 * (size_t)(rows * cols > 0 ? rows * cols : 1));
+    if (!Y) return NULL;
+    for (int64_t c = 0; c < cols; ++c) {
+        for (int64_t r = 0; r < rows; ++r) {
+            const double *src;
+            if (op == 0 || op == 3) src = X + 4 * (r + c * ldx);   /* X_{r c}            */
+            else                    src = X + 4 * (c + r * ldx);   /* X_{c r} (transpose) */
+            double *dst = Y + 4 * (r + c * rows);
+            if (op == 2 || op == 3) conj_q(src, dst);
+            else memcpy(dst, src, 4 * sizeof(double));
+        }
+    }
+    return Y;
+}
+
+/* C <- alpha * op(A) * op(B) + beta * C  over the quaternions.
+ * op(A) is M x K, op(B) is K x N, C is M x N (leading dimension ldc).
+ * Following the definition of the left scalar product, the sum over kappa is
+ * formed first and alpha multiplies it from the left; beta multiplies the old
+ * C from the left.  Loop order follows Alg. 1 (reference GEMM): columns nu of C
+ * outermost, then kappa, then the rows mu of the column.  Columns are
+ * independent, so they are split over OpenMP threads.
+ * Semantics this build chooses where the paper is silent: when beta is exactly
+ * zero (all four components) the old C is not read, so NaN/Inf in C do not
+ * propagate; K == 0 gives C <- beta C.
+ * Returns 0 on success, -1 on allocation failure, -2 on a bad op code. */
+int oracle_qgemm(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                 const double *alpha, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, const double *beta,
+                 double *C, int64_t ldc)
+{
+    if (opA < 0 || opA > 3 || opB < 0 || opB > 3) return -2;
+    if (M <= 0 || N <= 0) return 0;
+    const int beta_zero = (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0 && beta[3] == 0.0);
+    double *opa = materialise_op(opA, M, K, A, lda);
+    double *opb = materialise_op(opB, K, N, B, ldb);
+    if (!opa || !opb) { free(opa); free(opb); return -1; }
+    int failed = 0;
+#pragma omp parallel
+    {
+        double *acc = (double *)malloc(sizeof(double) * 4 * (size_t)M);
+        if (!acc) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t nu = 0; nu < N; ++nu) {
+            if (!acc) continue;
+            memset(acc, 0, sizeof(double) * 4 * (size_t)M);
+            for (int64_t ka = 0; ka < K; ++ka) {
+                const double *b = opb + 4 * (ka + nu * K);
+                for (int64_t mu = 0; mu < M; ++mu) {
+                    double t[4];
+                    oracle_hamilton(opa + 4 * (mu + ka * M), b, t);
+                    acc[4 * mu + 0] += t[0];
+                    acc[4 * mu + 1] += t[1];
+                    acc[4 * mu + 2] += t[2];
+                    acc[4 * mu + 3] += t[3];
+                }
+            }
+            for (int64_t mu = 0; mu < M; ++mu) {
+                double *c = C + 4 * (mu + nu * ldc);
+                double s[4], u[4] = {0.0, 0.0, 0.0, 0.0};
+                oracle_hamilton(alpha, acc + 4 * mu, s);
+                if (!beta_zero) oracle_hamilton(beta, c, u);
+                c[0] = s[0] + u[0];
+                c[1] = s[1] + u[1];
+                c[2] = s[2] + u[2];
+                c[3] = s[3] + u[3];
+            }
+        }
+        free(acc);
+    }
+    free(opa);
+    free(opb);
+    return failed ? -1 : 0;
+}
+
+/* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
+ * Euclidean inner product of the four components) for
+ *   C = alpha op(A) op(B) + beta C0.
+ * Derivation (a reading of this build; the paper has no gradient): for one
+ * term, <g, alpha a b> = Re(conj(g) alpha a b) is linear in a and in b, and
+ * cycling the real part gives
+ *   dL/d op(A)_{mu k} = sum_nu  conj(alpha) G_{mu nu} conj(op(B)_{k nu})
+ *   dL/d op(B)_{k nu} = sum_mu  conj(op(A)_{mu k}) conj(alpha) G_{mu nu}
+ *   dL/d C0_{mu nu}   = conj(beta) G_{mu nu}.
+ * The gradient of the stored operand follows from op: N -> same matrix,
+ * T -> its transpose, C -> its conjugate transpose, R -> its conjugate.
+ * Any of dA, dB, dC0 may be NULL (not computed).  Written as explicit loops:
+ * no blocking, no shared code with oracle_qgemm beyond the scalar product.
+ * Returns 0, -1 (allocation) or -2 (bad op). */
+int oracle_qgemm_backward(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                          const double *alpha, const double *A, int64_t lda,
+                          const double *B, int64_t ldb, const double *G, int64_t ldg,
+                          const double *beta,
+                          double *dA, int64_t ldda, double *dB, int64_t lddb,
+                          double *dC0, int64_t lddc0)
+{
+    if (opA < 0 || opA > 3 || opB < 0 || opB > 3) return -2;
+    double ca[4], cb[4];
+    conj_q(alpha, ca);
+    conj_q(beta, cb);
+    double *opa = materialise_op(opA, M, K, A, lda);
+    double *opb = materialise_op(opB, K, N, B, ldb);
+    if (!opa || !opb) { free(opa); free(opb); return -1; }
+    if (dA && M > 0 && K > 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t ka = 0; ka < K; ++ka) {
+            for (int64_t mu = 0; mu < M; ++mu) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int64_t nu = 0; nu < N; ++nu) {
+                    double cbq[4], t[4], u[4];
+                    conj_q(opb + 4 * (ka + nu * K), cbq);
+                    oracle_hamilton(G + 4 * (mu + nu * ldg), cbq, t);
+                    oracle_hamilton(ca, t, u);
+                    acc[0] += u[0]; acc[1] += u[1]; acc[2] += u[2]; acc[3] += u[3];
+                }
+                /* acc is dL/d op(A)_{mu ka}; place it in the stored layout */
+                double *dst;
+                if (opA == 0 || opA == 3) dst = dA + 4 * (mu + ka * ldda);
+                else                      dst = dA + 4 * (ka + mu * ldda);
+                if (opA == 2 || opA == 3) conj_q(acc, dst);
+                else memcpy(dst, acc, sizeof acc);
+            }
+        }
+    }
+    if (dB && K > 0 && N > 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t nu = 0; nu < N; ++nu) {
+            for (int64_t ka = 0; ka < K; ++ka) {
+                double acc[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int64_t mu = 0; mu < M; ++mu) {
+                    double caq[4], t[4], u[4];
+                    conj_q(opa + 4 * (mu + ka * M), caq);
+                    oracle_hamilton(ca, G + 4 * (mu + nu * ldg), t);
+                    oracle_hamilton(caq, t, u);
+                    acc[0] += u[0]; acc[1] += u[1]; acc[2] += u[2]; acc[3] += u[3];
+                }
+                double *dst;
+                if (opB == 0 || opB == 3) dst = dB + 4 * (ka + nu * lddb);
+                else                      dst = dB + 4 * (nu + ka * lddb);
+                if (opB == 2 || opB == 3) conj_q(acc, dst);
+                else memcpy(dst, acc, sizeof acc);
+            }
+        }
+    }
+    if (dC0) {
+        for (int64_t nu = 0; nu < N; ++nu)
+            for (int64_t mu = 0; mu < M; ++mu)
+                oracle_hamilton(cb, G + 4 * (mu + nu * ldg), dC0 + 4 * (mu + nu * lddc0));
+    }
+    free(opa);
+    free(opb);
+    return 0;
+}

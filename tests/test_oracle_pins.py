@@ -1,0 +1,459 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every check here uses a route other than the oracle's own formula: the basis
+table printed as the algebra's defining relations, the 2x2 complex
+representation (scalar and matrix, block and Kronecker forms), numpy complex
+and real matrix products, the complex and real sub-algebras, brute force over
+the basis table on tiny inputs, algebraic identities, and finite differences /
+torch autograd for the gradient.  A mutation test at the end plants mistakes
+in a copy of the oracle and checks these pins catch each one.
+"""
+import ctypes
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests import qref
+
+RNG = np.random.default_rng(20190314)
+
+
+def rq(n=None):
+    return RNG.standard_normal(4 if n is None else (n, 4))
+
+
+# ---------------------------------------------------------------- scalar algebra
+def test_basis_table_exact():
+    """e_i e_j for all 16 basis pairs equals the table of Eq. quaternion_alg."""
+    T = qref.basis_table()
+    E = np.eye(4)
+    for i in range(4):
+        for j in range(4):
+            assert np.array_equal(oracle.hamilton(E[i], E[j]), T[i, j]), (i, j)
+
+
+def test_basis_relations():
+    """i^2 = j^2 = k^2 = ijk = -1 and e_i e_j = -e_j e_i (Sec. 2.1)."""
+    E = np.eye(4)
+    m1 = -E[0]
+    for i in (1, 2, 3):
+        assert np.array_equal(oracle.hamilton(E[i], E[i]), m1)
+    assert np.array_equal(oracle.hamilton(oracle.hamilton(E[1], E[2]), E[3]), m1)
+    for i in (1, 2, 3):
+        for j in (1, 2, 3):
+            if i != j:
+                assert np.array_equal(oracle.hamilton(E[i], E[j]), -oracle.hamilton(E[j], E[i]))
+
+
+def test_levi_civita_table_consistent():
+    """The golden table agrees with -delta_ij e0 + eps_ijk e_k computed from
+    permutation parity (an independent statement of the same relation)."""
+    T = qref.basis_table()
+    for i in (1, 2, 3):
+        for j in (1, 2, 3):
+            want = np.zeros(4)
+            if i == j:
+                want[0] = -1.0
+            for k in (1, 2, 3):
+                perm = [i, j, k]
+                if len(set(perm)) == 3:
+                    P = np.zeros((3, 3))
+                    for r, c in enumerate(perm):
+                        P[r, c - 1] = 1
+                    want[k] += round(np.linalg.det(P))
+            assert np.array_equal(T[i, j], want)
+
+
+def test_product_matches_basis_expansion():
+    for _ in range(200):
+        p, q = rq(), rq()
+        np.testing.assert_allclose(oracle.hamilton(p, q), qref.bf_mul(p, q), rtol=0, atol=1e-14)
+
+
+def test_norm_multiplicative():
+    """|pq| = |p||q|: the quaternions are a normed division algebra."""
+    for _ in range(200):
+        p, q = rq(), rq()
+        assert abs(np.linalg.norm(oracle.hamilton(p, q)) - np.linalg.norm(p) * np.linalg.norm(q)) \
+            <= 1e-14 * np.linalg.norm(p) * np.linalg.norm(q)
+
+
+def test_associative():
+    for _ in range(200):
+        p, q, r = rq(), rq(), rq()
+        lhs = oracle.hamilton(oracle.hamilton(p, q), r)
+        rhs = oracle.hamilton(p, oracle.hamilton(q, r))
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13)
+
+
+def test_commutator_cross_product():
+    """[p,q] = sum eps_ijk (p_i q_j - p_j q_i) e_k = 2 (vec p x vec q), zero scalar part."""
+    for _ in range(100):
+        p, q = rq(), rq()
+        com = oracle.hamilton(p, q) - oracle.hamilton(q, p)
+        want = np.concatenate([[0.0], 2.0 * np.cross(p[1:], q[1:])])
+        np.testing.assert_allclose(com, want, rtol=0, atol=1e-13)
+    # non-commutative in general
+    p, q = rq(), rq()
+    assert np.abs(oracle.hamilton(p, q) - oracle.hamilton(q, p)).max() > 1e-3
+
+
+def test_conjugate_reverses_product():
+    """conj(pq) = conj(q) conj(p), and q conj(q) = |q|^2 e0."""
+    for _ in range(50):
+        p, q = rq(), rq()
+        lhs = np.asarray(qref.bf_conj(oracle.hamilton(p, q)))
+        rhs = oracle.hamilton(qref.bf_conj(q), qref.bf_conj(p))
+        np.testing.assert_allclose(lhs, rhs, atol=1e-13)
+        np.testing.assert_allclose(oracle.hamilton(q, qref.bf_conj(q)), [q @ q, 0, 0, 0], atol=1e-13)
+
+
+def test_complex_representation_homomorphism():
+    """(pq)_C = p_C q_C for the 2x2 complex representation (Eqs. h_matrep, hc_mult),
+    whose block and Pauli forms agree (Eq. pauli)."""
+    for _ in range(100):
+        p, q = rq(), rq()
+        np.testing.assert_allclose(qref.complex_rep_scalar(p), qref.complex_rep_pauli(p), atol=0)
+        lhs = qref.complex_rep_scalar(oracle.hamilton(p, q))
+        rhs = qref.complex_rep_scalar(p) @ qref.complex_rep_scalar(q)
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13)
+
+
+def test_complex_subalgebra():
+    """q2 = q3 = 0 behaves exactly as C (Eqs. complex_subalg, h_c_iso)."""
+    for _ in range(100):
+        a, b = RNG.standard_normal(2), RNG.standard_normal(2)
+        z = complex(*a) * complex(*b)
+        got = oracle.hamilton([a[0], a[1], 0, 0], [b[0], b[1], 0, 0])
+        np.testing.assert_allclose(got, [z.real, z.imag, 0, 0], atol=1e-14)
+
+
+def test_flop_table_and_metric():
+    """Tab. hc_flops / hc_mat_flops: quaternion multiply = 16 multiply-adds vs 32
+    for the complex 2x2 form; the throughput metric counts 2 flops per
+    multiply-add, i.e. 32 M N K."""
+    rows = {}
+    for line in open(os.path.join(qref.GOLDEN, "flop_counts.txt")):
+        line = line.split("#")[0].split()
+        if line:
+            rows[line[0]] = (int(line[1]), int(line[2]))
+    assert rows["scalar_mul"] == (16, 32)
+    assert rows["matrix_mul_per_N3"] == (16, 32)
+    # the complex 2x2 product of generic matrices: 8 complex MACs = 32 real MACs
+    assert 8 * 4 == rows["scalar_mul"][1]
+    from paper_1903_05575_amd import flops as qflops   # host-only helper
+    assert qflops(3, 5, 7) == 2 * rows["matrix_mul_per_N3"][0] * 3 * 5 * 7
+
+
+# ---------------------------------------------------------------- matrix level
+def _logical(X, r, c):
+    return qref.logical(X, r, c)
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (3, 5, 4), (7, 2, 9), (16, 16, 16), (33, 17, 40)])
+def test_gemm_vs_complex_embedding(M, N, K):
+    p = W.gemm_problem(11 + M + 3 * N + 7 * K, M, N, K, "N", "N", dist="normal")
+    got = oracle.qgemm("N", "N", M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"],
+                       p["beta"], p["C"], p["ldc"])
+    want = qref.qgemm_via_complex("N", "N", M, N, K, p["alpha"], p["A"], p["B"], p["beta"],
+                                  _logical(p["C"], M, N))
+    np.testing.assert_allclose(_logical(got, M, N), want, rtol=0, atol=1e-12 * max(1, K))
+
+
+def test_gemm_kron_form_homomorphism():
+    """The Kronecker form of Eq. qmat_complex is also multiplicative, and equals
+    the block form up to a perfect-shuffle permutation of rows and columns."""
+    M, N, K = 5, 4, 6
+    p = W.gemm_problem(5, M, N, K, "N", "N", dist="normal",
+                       alpha=[1, 0, 0, 0], beta=[0, 0, 0, 0])
+    got = _logical(oracle.qgemm("N", "N", M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"],
+                                p["beta"], p["C"], p["ldc"]), M, N)
+    A, B = _logical(p["A"], M, K), _logical(p["B"], K, N)
+    np.testing.assert_allclose(qref.complex_rep_kron(got),
+                               qref.complex_rep_kron(A) @ qref.complex_rep_kron(B), atol=1e-12)
+    # shuffle: kron index 2*r + s  <->  block index s*R + r
+    def shuffle(R):
+        return np.array([2 * r + s for s in range(2) for r in range(R)])
+    Kr, Bl = qref.complex_rep_kron(got), qref.complex_rep_block(got)
+    np.testing.assert_array_equal(Kr[np.ix_(shuffle(M), shuffle(N))], Bl)
+
+
+@pytest.mark.parametrize("opA", "NTCR")
+@pytest.mark.parametrize("opB", "NTCR")
+def test_gemm_all_ops_brute_force(opA, opB):
+    """Tiny problems with random quaternion alpha, beta and padded leading
+    dimensions against pure-Python brute force over the basis table."""
+    M, N, K = 3, 4, 5
+    p = W.gemm_problem(100 + "NTCR".index(opA) * 4 + "NTCR".index(opB), M, N, K, opA, opB,
+                       dist="normal", pad=2)
+    got = oracle.qgemm(opA, opB, M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"],
+                       p["beta"], p["C"], p["ldc"])
+    want = qref.bf_qgemm(opA, opB, M, N, K, p["alpha"], p["A"], p["B"], p["beta"],
+                         _logical(p["C"], M, N))
+    np.testing.assert_allclose(_logical(got, M, N), want, rtol=0, atol=1e-12)
+    # padding rows of C are untouched (NaN stays NaN, nothing else written)
+    assert np.isnan(got[:, M:, :]).all()
+
+
+def test_conjugate_transpose_via_complex():
+    """(A^H)_C = (A_C)^H: op C agrees with numpy's conjugate transpose of the
+    complex representation (Sec. 2.2)."""
+    M, N, K = 6, 5, 7
+    p = W.gemm_problem(77, M, N, K, "C", "C", dist="normal", alpha=[1, 0, 0, 0], beta=[0, 0, 0, 0])
+    got = _logical(oracle.qgemm("C", "C", M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"],
+                                p["beta"], p["C"], p["ldc"]), M, N)
+    As = _logical(p["A"], K, M)        # stored A is K x M
+    Bs = _logical(p["B"], N, K)        # stored B is N x K
+    want = qref.complex_rep_block(As).conj().T @ qref.complex_rep_block(Bs).conj().T
+    np.testing.assert_allclose(qref.complex_rep_block(got), want, atol=1e-12)
+
+
+def test_transpose_does_not_distribute():
+    """(AB)^H = B^H A^H holds over the quaternions but (AB)^T != B^T A^T."""
+    M, N, K = 4, 3, 5
+    g = W.rng(3)
+    A = W.qmatrix(g, M, K)
+    B = W.qmatrix(g, K, N)
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    AB = oracle.qgemm("N", "N", M, N, K, one, A, M, B, K, zero, np.zeros((N, M, 4)), M)
+    BhAh = oracle.qgemm("C", "C", N, M, K, one, B, K, A, M, zero, np.zeros((M, N, 4)), N)
+    np.testing.assert_allclose(_logical(BhAh, N, M),
+                               _logical(AB, M, N).transpose(1, 0, 2) * [1, -1, -1, -1], atol=1e-12)
+    BtAt = oracle.qgemm("T", "T", N, M, K, one, B, K, A, M, zero, np.zeros((M, N, 4)), N)
+    assert np.abs(_logical(BtAt, N, M) - _logical(AB, M, N).transpose(1, 0, 2)).max() > 1e-2
+
+
+def test_matrix_associativity():
+    M, N, K, L = 5, 6, 7, 4
+    g = W.rng(9)
+    A, B, C = W.qmatrix(g, M, K), W.qmatrix(g, K, L), W.qmatrix(g, L, N)
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    AB = oracle.qgemm("N", "N", M, L, K, one, A, M, B, K, zero, np.zeros((L, M, 4)), M)
+    BC = oracle.qgemm("N", "N", K, N, L, one, B, K, C, L, zero, np.zeros((N, K, 4)), K)
+    l = oracle.qgemm("N", "N", M, N, L, one, AB, M, C, L, zero, np.zeros((N, M, 4)), M)
+    r = oracle.qgemm("N", "N", M, N, K, one, A, M, BC, K, zero, np.zeros((N, M, 4)), M)
+    np.testing.assert_allclose(l, r, atol=1e-11)
+
+
+def test_matrix_subalgebras():
+    """Complex-valued quaternion matrices multiply as complex matrices
+    (Eq. h_c_mat_iso); real-valued ones as real matrices."""
+    M, N, K = 9, 8, 10
+    g = W.rng(21)
+    A, B = W.qmatrix(g, M, K), W.qmatrix(g, K, N)
+    A[..., 2:] = 0.0
+    B[..., 2:] = 0.0
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    got = _logical(oracle.qgemm("N", "N", M, N, K, one, A, M, B, K, zero, np.zeros((N, M, 4)), M), M, N)
+    ZA = _logical(A, M, K)[..., 0] + 1j * _logical(A, M, K)[..., 1]
+    ZB = _logical(B, K, N)[..., 0] + 1j * _logical(B, K, N)[..., 1]
+    Z = ZA @ ZB
+    np.testing.assert_allclose(got, np.stack([Z.real, Z.imag, 0 * Z.real, 0 * Z.real], -1), atol=1e-12)
+    A[..., 1] = 0.0
+    B[..., 1] = 0.0
+    got = _logical(oracle.qgemm("N", "N", M, N, K, one, A, M, B, K, zero, np.zeros((N, M, 4)), M), M, N)
+    R = _logical(A, M, K)[..., 0] @ _logical(B, K, N)[..., 0]
+    np.testing.assert_allclose(got[..., 0], R, atol=1e-12)
+    assert np.abs(got[..., 1:]).max() == 0.0
+
+
+def test_identity_and_basis_matrices():
+    """A I = A; (e_k I) B = e_k B elementwise."""
+    M, K = 6, 6
+    g = W.rng(4)
+    A = W.qmatrix(g, M, K)
+    I = np.zeros((K, K, 4))
+    for i in range(K):
+        I[i, i, 0] = 1.0
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    got = oracle.qgemm("N", "N", M, K, K, one, A, M, I, K, zero, np.zeros((K, M, 4)), M)
+    np.testing.assert_array_equal(got, A)
+    for k in (1, 2, 3):
+        Ek = np.zeros((K, M, 4))
+        for i in range(M):
+            Ek[i, i, k] = 1.0
+        got = oracle.qgemm("N", "N", M, K, M, one, Ek, M, A, M, zero, np.zeros((K, M, 4)), M)
+        for mu in range(M):
+            for nu in range(K):
+                np.testing.assert_allclose(got[nu, mu], qref.bf_mul(np.eye(4)[k], A[nu, mu]), atol=0)
+
+
+def test_scalar_side_left():
+    """alpha multiplies from the left: qgemm(alpha = e1) = e1 (AB) != (AB) e1
+    (Sec. 2.2 left/right scalar products; Sec. 3.1 note on alpha placement)."""
+    M, N, K = 4, 5, 6
+    g = W.rng(8)
+    A, B = W.qmatrix(g, M, K), W.qmatrix(g, K, N)
+    e1, zero, one = np.array([0.0, 1, 0, 0]), np.zeros(4), np.array([1.0, 0, 0, 0])
+    AB = _logical(oracle.qgemm("N", "N", M, N, K, one, A, M, B, K, zero, np.zeros((N, M, 4)), M), M, N)
+    got = _logical(oracle.qgemm("N", "N", M, N, K, e1, A, M, B, K, zero, np.zeros((N, M, 4)), M), M, N)
+    left = np.array([[qref.bf_mul(e1, AB[i, j]) for j in range(N)] for i in range(M)])
+    right = np.array([[qref.bf_mul(AB[i, j], e1) for j in range(N)] for i in range(M)])
+    np.testing.assert_allclose(got, left, atol=1e-12)
+    assert np.abs(got - right).max() > 1e-2
+
+
+def test_beta_zero_ignores_nan_and_k_zero():
+    M, N, K = 4, 3, 5
+    g = W.rng(6)
+    A, B = W.qmatrix(g, M, K), W.qmatrix(g, K, N)
+    C = np.full((N, M, 4), np.nan)
+    al = np.array([0.3, -0.2, 0.5, 0.1])
+    got = oracle.qgemm("N", "N", M, N, K, al, A, M, B, K, np.zeros(4), C, M)
+    assert np.isfinite(got).all()
+    C = W.qmatrix(g, M, N)
+    be = np.array([0.5, 0.25, -1.0, 2.0])
+    got = oracle.qgemm("N", "N", M, N, 0, al, A, M, B, K, be, C, M)
+    want = np.array([[qref.bf_mul(be, C[j, i]) for i in range(M)] for j in range(N)])
+    np.testing.assert_allclose(got, want, atol=1e-14)
+    # M == 0 / N == 0: no-op
+    got = oracle.qgemm("N", "N", 0, N, K, al, A, 1, B, K, be, C, 1)
+    np.testing.assert_array_equal(got, C)
+
+
+def test_sampled_entries_helper():
+    """qgemm_entries equals the corresponding entries of the full product."""
+    M, N, K = 13, 11, 9
+    for opA in "NTC":
+        for opB in "NTC":
+            p = W.gemm_problem(300, M, N, K, opA, opB, pad=1)
+            full = oracle.qgemm(opA, opB, M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"],
+                                p["beta"], p["C"], p["ldc"])
+            rows, cols = np.array([0, 5, 12]), np.array([10, 1])
+            part = oracle.qgemm_entries(opA, opB, K, p["alpha"], p["A"], p["B"], p["beta"], p["C"],
+                                        rows, cols)
+            np.testing.assert_allclose(part, full[cols][:, rows], rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------- gradient
+def _loss(opA, opB, M, N, K, al, A, lda, B, ldb, G, be, C0):
+    out = oracle.qgemm(opA, opB, M, N, K, al, A, lda, B, ldb, be, C0, M)
+    return float(np.sum(qref.logical(out, M, N) * qref.logical(G, M, N)))
+
+
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C"), ("C", "T"), ("R", "N"), ("N", "R"), ("C", "C")])
+def test_backward_finite_differences(opA, opB):
+    """The loss <G, alpha op(A) op(B) + beta C0> is bilinear in (A, B) and linear
+    in C0, so central differences with h = 1 are exact up to rounding."""
+    M, N, K = 3, 4, 2
+    p = W.gemm_problem(500 + "NTCR".index(opA) * 4 + "NTCR".index(opB), M, N, K, opA, opB,
+                       dist="normal")
+    g = W.rng(91)
+    G = W.qmatrix(g, M, N)
+    C0 = p["C"]
+    dA, dB, dC0 = oracle.qgemm_backward(opA, opB, M, N, K, p["alpha"], p["A"], p["lda"],
+                                        p["B"], p["ldb"], G, M, p["beta"])
+    args = (p["alpha"],)
+    for name, X, dX in (("A", p["A"], dA), ("B", p["B"], dB), ("C0", C0, dC0)):
+        cols, rows = X.shape[0], X.shape[1]
+        for c in range(cols):
+            for r in range(rows):
+                for comp in range(4):
+                    Xp, Xm = X.copy(), X.copy()
+                    Xp[c, r, comp] += 1.0
+                    Xm[c, r, comp] -= 1.0
+                    kw = dict(A=p["A"], B=p["B"], C0=C0)
+                    kw[name] = Xp
+                    lp = _loss(opA, opB, M, N, K, args[0], kw["A"], p["lda"], kw["B"], p["ldb"], G, p["beta"], kw["C0"])
+                    kw[name] = Xm
+                    lm = _loss(opA, opB, M, N, K, args[0], kw["A"], p["lda"], kw["B"], p["ldb"], G, p["beta"], kw["C0"])
+                    assert abs((lp - lm) / 2.0 - dX[c, r, comp]) < 1e-12, (name, c, r, comp)
+
+
+def test_backward_vs_torch_autograd_complex_embedding():
+    """Gradient of <G, X W> from torch autograd (CPU, fp64) through the complex
+    block representation (Eq. qmat_complex, hc_mat_mult), an independent route."""
+    torch = pytest.importorskip("torch")
+    M, N, K = 7, 6, 5
+    g = W.rng(31)
+    X, Wm, G = W.qmatrix(g, M, K), W.qmatrix(g, K, N), W.qmatrix(g, M, N)
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    dX, dW, _ = oracle.qgemm_backward("N", "N", M, N, K, one, X, M, Wm, K, G, M, zero, want_dC0=False)
+    xt = torch.tensor(qref.logical(X, M, K).copy(), dtype=torch.float64, requires_grad=True)
+    wt = torch.tensor(qref.logical(Wm, K, N).copy(), dtype=torch.float64, requires_grad=True)
+
+    def crep(Q):
+        z0 = torch.complex(Q[..., 0], Q[..., 1])
+        z1 = torch.complex(Q[..., 2], Q[..., 3])
+        return torch.cat([torch.cat([z0, z1], 1), torch.cat([-z1.conj(), z0.conj()], 1)], 0)
+
+    Yc = crep(xt) @ crep(wt)
+    Gl = torch.tensor(qref.logical(G, M, N).copy())
+    top0, top1 = Yc[:M, :N], Yc[:M, N:]
+    loss = (top0.real * Gl[..., 0] + top0.imag * Gl[..., 1] + top1.real * Gl[..., 2]
+            + top1.imag * Gl[..., 3]).sum()
+    loss.backward()
+    np.testing.assert_allclose(qref.logical(dX, M, K), xt.grad.numpy(), atol=1e-12)
+    np.testing.assert_allclose(qref.logical(dW, K, N), wt.grad.numpy(), atol=1e-12)
+
+
+# ---------------------------------------------------------------- mutation check
+MUTANTS = [
+    ("out[0] = p[0] * q[0] - (p[1] * q[1]", "out[0] = p[0] * q[0] + (p[1] * q[1]"),   # sign of dot part
+    ("(p[2] * q[3] - p[3] * q[2])", "(p[3] * q[2] - p[2] * q[3])"),                  # cross sign e1
+    ("(p[3] * q[1] - p[1] * q[3])", "(p[3] * q[1] - p[1] * q[2])"),                  # wrong index
+    ("oracle_hamilton(alpha, acc + 4 * mu, s);", "oracle_hamilton(acc + 4 * mu, alpha, s);"),  # alpha right
+    ("if (op == 2 || op == 3) conj_q(src, dst);", "if (op == 3) conj_q(src, dst);"),  # C forgets conj
+    ("else                    src = X + 4 * (c + r * ldx);", "else                    src = X + 4 * (r + c * ldx);"),  # T forgets transpose
+    ("if (!beta_zero) oracle_hamilton(beta, c, u);", "if (!beta_zero) oracle_hamilton(c, beta, u);"),  # beta right
+    ("for (int64_t ka = 0; ka < K; ++ka) {\n                const double *b", "for (int64_t ka = 1; ka < K; ++ka) {\n                const double *b"),  # dropped term
+]
+
+
+def _build_mutant(src, tmp, idx):
+    path = os.path.join(tmp, f"mut{idx}.c")
+    open(path, "w").write(src)
+    so = os.path.join(tmp, f"libmut{idx}.so")
+    subprocess.run(["gcc", "-O1", "-shared", "-fPIC", "-std=c99", "-o", so, path], check=True)
+    return so
+
+
+def _mutant_pins_fail(so):
+    """Run a few of the pins above against a mutant library; True if any fails."""
+    L = ctypes.CDLL(so)
+    dp = ctypes.POINTER(ctypes.c_double)
+    i64 = ctypes.c_int64
+    L.oracle_qgemm.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, i64, dp, dp, i64, dp, i64, dp, dp, i64]
+    L.oracle_hamilton.argtypes = [dp, dp, dp]
+
+    def P(a):
+        return a.ctypes.data_as(dp)
+
+    E = np.eye(4)
+    T = qref.basis_table()
+    for i in range(4):
+        for j in range(4):
+            o = np.zeros(4)
+            L.oracle_hamilton(P(np.ascontiguousarray(E[i])), P(np.ascontiguousarray(E[j])), P(o))
+            if not np.array_equal(o, T[i, j]):
+                return True
+    for opA in "NTCR":
+        for opB in "NTCR":
+            M, N, K = 3, 4, 5
+            p = W.gemm_problem(7, M, N, K, opA, opB, dist="normal", pad=1)
+            out = np.ascontiguousarray(p["C"].copy())
+            L.oracle_qgemm("NTCR".index(opA), "NTCR".index(opB), M, N, K, P(p["alpha"]), P(p["A"]), p["lda"],
+                           P(p["B"]), p["ldb"], P(p["beta"]), P(out), p["ldc"])
+            want = qref.bf_qgemm(opA, opB, M, N, K, p["alpha"], p["A"], p["B"], p["beta"],
+                                 qref.logical(p["C"], M, N))
+            if not np.allclose(qref.logical(out, M, N), want, atol=1e-12):
+                return True
+    return False
+
+
+def test_pins_catch_planted_mistakes():
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "qgemm_oracle.c")).read()
+    with tempfile.TemporaryDirectory() as tmp:
+        clean = _build_mutant(src, tmp, "clean")
+        assert not _mutant_pins_fail(clean)
+        for idx, (old, new) in enumerate(MUTANTS):
+            assert src.count(old) == 1, old
+            assert _mutant_pins_fail(_build_mutant(src.replace(old, new), tmp, idx)), old
