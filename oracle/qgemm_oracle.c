@@ -107,9 +107,10 @@ static double *materialise_op(int op, int64_t rows, int64_t cols,
  * C from the left.  Loop order follows Alg. 1 (reference GEMM): columns nu of C
  * outermost, then kappa, then the rows mu of the column.  Columns are
  * independent, so they are split over OpenMP threads.
- * Semantics this build chooses where the paper is silent: when beta is exactly
- * zero (all four components) the old C is not read, so NaN/Inf in C do not
- * propagate; K == 0 gives C <- beta C.
+ * Semantics this build chooses where the paper is silent (the BLAS
+ * convention): when beta is exactly zero (all four components) the old C is
+ * not read, so NaN/Inf in C do not propagate; when alpha is exactly zero or
+ * K == 0 the product is not formed and A, B are not read, giving C <- beta C.
  * Returns 0 on success, -1 on allocation failure, -2 on a bad op code. */
 int oracle_qgemm(int opA, int opB, int64_t M, int64_t N, int64_t K,
                  const double *alpha, const double *A, int64_t lda,
@@ -119,6 +120,8 @@ int oracle_qgemm(int opA, int opB, int64_t M, int64_t N, int64_t K,
     if (opA < 0 || opA > 3 || opB < 0 || opB > 3) return -2;
     if (M <= 0 || N <= 0) return 0;
     const int beta_zero = (beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0 && beta[3] == 0.0);
+    const int alpha_zero = (alpha[0] == 0.0 && alpha[1] == 0.0 && alpha[2] == 0.0 && alpha[3] == 0.0);
+    if (alpha_zero) K = 0;
     double *opa = materialise_op(opA, M, K, A, lda);
     double *opb = materialise_op(opB, K, N, B, ldb);
     if (!opa || !opb) { free(opa); free(opb); return -1; }

@@ -312,6 +312,10 @@ def test_beta_zero_ignores_nan_and_k_zero():
     got = oracle.qgemm("N", "N", M, N, 0, al, A, M, B, K, be, C, M)
     want = np.array([[qref.bf_mul(be, C[j, i]) for i in range(M)] for j in range(N)])
     np.testing.assert_allclose(got, want, atol=1e-14)
+    # alpha == 0: A and B are not read (NaN there does not reach C)
+    An, Bn = np.full_like(A, np.nan), np.full_like(B, np.nan)
+    got = oracle.qgemm("N", "N", M, N, K, np.zeros(4), An, M, Bn, K, be, C, M)
+    np.testing.assert_allclose(got, want, atol=1e-14)
     # M == 0 / N == 0: no-op
     got = oracle.qgemm("N", "N", 0, N, K, al, A, 1, B, K, be, C, 1)
     np.testing.assert_array_equal(got, C)
