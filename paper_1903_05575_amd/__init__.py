@@ -1,4 +1,15 @@
-"""MI355X-native quaternion GEMM (placeholder; binding added with the C-ABI)."""
+"""MI355X-native quaternion GEMM: C <- alpha op(A) op(B) + beta C.
+
+The computation runs in hand-written HIP kernels for gfx950 behind the C ABI
+of ``libqgemm.so`` (include/qgemm.h).  This package is the thin Python
+binding: it marshals torch GPU tensors (used only for device memory and
+streams) to that ABI.
+
+Storage: a rows x cols quaternion matrix with leading dimension ld is a
+contiguous tensor of shape (cols, ld, 4): column-major, four interleaved
+components (q0, q1, q2, q3) per element.
+"""
+from ._lib import QGemmError, lib, qgemm_d, exported_symbols  # noqa: F401
 
 
 def flops(M, N, K):

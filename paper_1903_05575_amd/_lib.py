@@ -1,0 +1,118 @@
+"""ctypes binding of libqgemm.so (argument marshalling only).
+
+Every step of the computation runs in the HIP kernels behind the C ABI
+declared in include/qgemm.h; this module converts Python arguments to the
+C types, checks that tensors are large enough for the sizes passed, and turns
+status codes into exceptions.  There is no fallback: if the library is
+missing or cannot be loaded, every call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqgemm.so")
+
+OPS = {"N": 0, "T": 1, "C": 2, "R": 3}
+STATUS = {0: "QGEMM_OK", 1: "QGEMM_ERR_INVALID_ARG", 2: "QGEMM_ERR_MISALIGNED", 3: "QGEMM_ERR_HIP",
+          4: "QGEMM_ERR_ALLOC", 5: "QGEMM_ERR_UNSUPPORTED"}
+
+
+class QGemmError(RuntimeError):
+    def __init__(self, status, arg, where):
+        self.status = status
+        self.arg = arg
+        super().__init__(f"{where}: {STATUS.get(status, status)} (argument {arg})")
+
+
+_lib = None
+
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGNATURES = {
+    "qgemm_status_string": ([_int], ctypes.c_char_p),
+    "qgemm_last_invalid_arg": ([], _int),
+    "qgemm_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
+}
+
+
+def lib():
+    """Load libqgemm.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1903_05575_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def _q4(x):
+    a = (ctypes.c_double * 4)(*[float(v) for v in x])
+    return ctypes.cast(a, _dp), a
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check_storage(t, rows, cols, ld, dtype, name):
+    """A stored rows x cols operand needs (cols-1)*ld + rows quaternions."""
+    if rows == 0 or cols == 0:
+        return
+    if t is None:
+        raise ValueError(f"{name} is None")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    need = 4 * ((cols - 1) * ld + rows)
+    if t.numel() < need:
+        raise ValueError(f"{name} holds {t.numel()} reals, needs {need}")
+
+
+def _stored(op, rows, cols):
+    return (rows, cols) if op in ("N", "R") else (cols, rows)
+
+
+def _raise(rc, where):
+    if rc != 0:
+        raise QGemmError(rc, lib().qgemm_last_invalid_arg(), where)
+
+
+def qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    """C <- alpha op(A) op(B) + beta C in binary64 (C-ABI qgemm_d).
+    A, B, C are float64 GPU tensors in column-major interleaved storage."""
+    ra, ca = _stored(opA, M, K)
+    rb, cb = _stored(opB, K, N)
+    if M and N and K:
+        _check_storage(A, ra, ca, lda, torch.float64, "A")
+        _check_storage(B, rb, cb, ldb, torch.float64, "B")
+    _check_storage(C, M, N, ldc, torch.float64, "C")
+    pa, _ka = _q4(alpha)
+    pb, _kb = _q4(beta)
+    rc = lib().qgemm_d(OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb, pb, _ptr(C), ldc,
+                       _stream(stream))
+    _raise(rc, "qgemm_d")

@@ -1,0 +1,250 @@
+// FP64 quaternion GEMM on the gfx950 FP64 matrix cores.
+//
+// Method.  Write a quaternion a as the real 4x4 block L(a) with
+// vec(a b) = L(a) vec(b) (from Eq. quaternion_prod).  Then, with B and C read
+// as real matrices of 4K x N and 4M x N reals (the interleaved column-major
+// storage already is that), C_real = L(op A) B_real: a real GEMM of shape
+// (4M, N, 4K) doing exactly 16 real multiply-adds per quaternion
+// multiply-add, the count of Tab. hc_flops.  L(op A) is never materialised:
+// each lane of the MFMA A operand picks one component of one quaternion from
+// LDS and flips its sign, so the expansion costs no HBM traffic and no flops.
+//
+// MFMA.  v_mfma_f64_16x16x4_f64 computes D(16x16) += A(16x4) B(4x16) with
+//   A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, and D[i][j] in lane
+//   j + 16 (i % 4), register i / 4 (layout measured on gfx950).
+// Row i of the A operand is mapped to quaternion row  mu = i % 4  and
+// component r = i / 4, column k to component c of op(B).  Then lane l of the
+// result holds all four components (registers 0..3) of output quaternion
+// (mu0 + l / 16, nu0 + l % 16), so the non-commuting alpha/beta epilogue is
+// lane-local.  One MFMA = 4 quaternion rows x 16 quaternion columns x one
+// kappa = 64 quaternion multiply-adds.
+//
+// Tiling (block = 256 threads = 4 waves, BM x BN = 64 x 64 quaternions):
+//   wave w owns quaternion rows [16w, 16w+16) x all 64 columns = 4 x 4 MFMA
+//   blocks, 16 accumulators of 4 doubles.  Per kappa a wave reads 4 A and 4 B
+//   fragments (one 8-byte LDS read per lane each) and issues 16 MFMAs.
+//   K is walked in tiles of BK = 8 quaternions through two LDS stages: the
+//   next tile is fetched from HBM into registers while the current one is
+//   multiplied, then written to the other stage (one barrier per tile).
+// LDS layouts (doubles):
+//   A stage: [kappa][mu][4] with a row pitch of 4*BM + 4 (the pad spreads the
+//            transposed-operand writes over the banks); fragment reads of one
+//            kappa touch 4 consecutive quaternions = 128 contiguous bytes.
+//   B stage: [kappa][component][nu], plane pitch BN + 1; a fragment read is
+//            16 consecutive doubles per component.  op(B) conjugation and the
+//            optional left scale s are applied while writing this stage.
+#include "qgemm_internal.hpp"
+
+namespace qg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int BM = 64, BN = 64, BK = 8;
+constexpr int NT = 256;
+constexpr int A_LD = 4 * BM + 4;                 // doubles per kappa row of the A stage
+constexpr int B_PL = BN + 1;                     // doubles per component plane of the B stage
+constexpr int A_STAGE = BK * A_LD;
+constexpr int B_STAGE = BK * 4 * B_PL;
+constexpr int STAGE = A_STAGE + B_STAGE;
+constexpr int A_CHUNKS = BM * BK * 2 / NT;       // 16-byte chunks of A per thread per tile
+constexpr int B_QUATS = BN * BK / NT;            // quaternions of B per thread per tile
+constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
+
+static_assert(A_CHUNKS * NT == BM * BK * 2, "A tile must split evenly over the block");
+static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
+
+__device__ __forceinline__ double flip(double v, unsigned long long sign)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ (long long)sign);
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n, int nk)
+{
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    int tm, tn;
+    xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    // ---- per-lane constants of the A fragment (row i = lane % 16, column c = lane / 16)
+    const int fi = lane & 15;
+    const int fr = fi >> 2;                      // component of the result row
+    const int fmu = fi & 3;                      // quaternion row within the 4-row block
+    const int fc = lane >> 4;                    // component of op(B) (k index)
+    const int fcomp = fr ^ fc;                   // component of a that L(a)[fr][fc] reads
+    const bool neg = l_negative(fr, fc) ^ (p.conjA && fcomp != 0);
+    const unsigned long long sgnA = neg ? 0x8000000000000000ull : 0ull;
+    const int a_off = (wave * 16 + fmu) * 4 + fcomp;      // + kk*A_LD + 16*m
+    const int b_off = fc * B_PL + (lane & 15);            // + kk*4*B_PL + 16*n
+
+    d4 acc[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    d2 ra[A_CHUNKS];
+    d2 rb[B_QUATS][2];
+
+    auto load_tile = [&](int kt) {
+        const int k0 = kt * BK;
+#pragma unroll
+        for (int i = 0; i < A_CHUNKS; ++i) {
+            const int q = tid + NT * i;
+            const int half = q & 1;
+            int mu, ka;
+            if (!TA) { mu = (q >> 1) % BM; ka = (q >> 1) / BM; }
+            else     { ka = (q >> 1) % BK; mu = (q >> 1) / BK; }
+            const int gm = m0 + mu, gk = k0 + ka;
+            if (gm < p.M && gk < p.K) {
+                const int64_t e = TA ? ((int64_t)gm * p.lda + gk) : ((int64_t)gk * p.lda + gm);
+                ra[i] = *reinterpret_cast<const d2 *>(p.A + 4 * e + 2 * half);
+            } else {
+                ra[i] = (d2){0.0, 0.0};
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < B_QUATS; ++i) {
+            const int q = tid + NT * i;
+            int nu, ka;
+            if (!TB) { ka = q % BK; nu = q / BK; }
+            else     { nu = q % BN; ka = q / BN; }
+            const int gn = n0 + nu, gk = k0 + ka;
+            if (gn < p.N && gk < p.K) {
+                const int64_t e = TB ? ((int64_t)gk * p.ldb + gn) : ((int64_t)gn * p.ldb + gk);
+                const d2 *src = reinterpret_cast<const d2 *>(p.B + 4 * e);
+                rb[i][0] = src[0];
+                rb[i][1] = src[1];
+            } else {
+                rb[i][0] = (d2){0.0, 0.0};
+                rb[i][1] = (d2){0.0, 0.0};
+            }
+        }
+    };
+
+    auto store_tile = [&](int stage) {
+        double *As = smem + stage * STAGE;
+        double *Bs = As + A_STAGE;
+#pragma unroll
+        for (int i = 0; i < A_CHUNKS; ++i) {
+            const int q = tid + NT * i;
+            const int half = q & 1;
+            int mu, ka;
+            if (!TA) { mu = (q >> 1) % BM; ka = (q >> 1) / BM; }
+            else     { ka = (q >> 1) % BK; mu = (q >> 1) / BK; }
+            *reinterpret_cast<d2 *>(As + ka * A_LD + mu * 4 + 2 * half) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < B_QUATS; ++i) {
+            const int q = tid + NT * i;
+            int nu, ka;
+            if (!TB) { ka = q % BK; nu = q / BK; }
+            else     { nu = q % BN; ka = q / BN; }
+            double b[4] = {rb[i][0].x, rb[i][0].y, rb[i][1].x, rb[i][1].y};
+            if (p.conjB) { b[1] = -b[1]; b[2] = -b[2]; b[3] = -b[3]; }
+            if (p.has_bscale) {
+                double t[4];
+                qmul(p.bscale, b, t);
+                b[0] = t[0]; b[1] = t[1]; b[2] = t[2]; b[3] = t[3];
+            }
+            double *dst = Bs + ka * 4 * B_PL + nu;
+            dst[0 * B_PL] = b[0];
+            dst[1 * B_PL] = b[1];
+            dst[2 * B_PL] = b[2];
+            dst[3 * B_PL] = b[3];
+        }
+    };
+
+    if (nk > 0) {
+        load_tile(0);
+        store_tile(0);
+        __syncthreads();
+    }
+    for (int kt = 0; kt < nk; ++kt) {
+        const int stage = kt & 1;
+        if (kt + 1 < nk) load_tile(kt + 1);
+        const double *As = smem + stage * STAGE;
+        const double *Bs = As + A_STAGE;
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) a[m] = flip(As[kk * A_LD + a_off + 16 * m], sgnA);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) b[n] = Bs[kk * 4 * B_PL + b_off + 16 * n];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+        }
+        if (kt + 1 < nk) store_tile(stage ^ 1);
+        __syncthreads();
+    }
+
+    // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions
+    const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int mu = m0 + wave * 16 + 4 * m + (lane >> 4);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int nu = n0 + 16 * n + (lane & 15);
+            if (mu < p.M && nu < p.N) {
+                const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
+                double o[4];
+                qmul(p.alpha, v, o);
+                if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
+                const int64_t e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
+                d2 *dst = reinterpret_cast<d2 *>(p.C + 4 * e);
+                if (!beta_zero) {
+                    const d2 c0 = dst[0], c1 = dst[1];
+                    const double cq[4] = {c0.x, c0.y, c1.x, c1.y};
+                    double u[4];
+                    qmul(p.beta, cq, u);
+                    o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
+                }
+                dst[0] = (d2){o[0], o[1]};
+                dst[1] = (d2){o[2], o[3]};
+            }
+        }
+    }
+}
+
+template <bool TA, bool TB>
+hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int tiles_m = (d.M + BM - 1) / BM;
+    const int tiles_n = (d.N + BN - 1) / BN;
+    const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
+    const int nk = alpha_zero ? 0 : (d.K + BK - 1) / BK;
+    const int64_t nblocks = (int64_t)tiles_m * tiles_n;
+    if (nblocks <= 0) return hipSuccess;
+    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,
+                       d, tiles_m, tiles_n, nk);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream)
+{
+    if (d.opA_t) return d.opB_t ? launch_t<true, true>(d, stream) : launch_t<true, false>(d, stream);
+    return d.opB_t ? launch_t<false, true>(d, stream) : launch_t<false, false>(d, stream);
+}
+
+}  // namespace qg

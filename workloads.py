@@ -75,13 +75,14 @@ def gemm_problem(seed, M, N, K, opA="N", opB="N", dist="uniform", dtype=np.float
     g = rng(seed)
     ra, ca = stored_dims(opA, M, K)
     rb, cb = stored_dims(opB, K, N)
-    A = qmatrix(g, ra, ca, ld=ra + pad, dist=dist, dtype=dtype)
-    B = qmatrix(g, rb, cb, ld=rb + pad, dist=dist, dtype=dtype)
-    C = qmatrix(g, M, N, ld=M + pad, dist=dist, dtype=dtype)
+    lda, ldb, ldc = max(ra, 1) + pad, max(rb, 1) + pad, max(M, 1) + pad
+    A = qmatrix(g, ra, ca, ld=lda, dist=dist, dtype=dtype)
+    B = qmatrix(g, rb, cb, ld=ldb, dist=dist, dtype=dtype)
+    C = qmatrix(g, M, N, ld=ldc, dist=dist, dtype=dtype)
     al = quaternion(g) if alpha is None else np.asarray(alpha, dtype=np.float64)
     be = quaternion(g) if beta is None else np.asarray(beta, dtype=np.float64)
-    return dict(opA=opA, opB=opB, M=M, N=N, K=K, alpha=al, beta=be, A=A, lda=ra + pad,
-                B=B, ldb=rb + pad, C=C, ldc=M + pad)
+    return dict(opA=opA, opB=opB, M=M, N=N, K=K, alpha=al, beta=be, A=A, lda=lda,
+                B=B, ldb=ldb, C=C, ldc=ldc)
 
 
 SWEEP_SIZES = (1024, 2048, 4096, 8192)
