@@ -37,6 +37,8 @@ _SIGNATURES = {
     "qgemm_status_string": ([_int], ctypes.c_char_p),
     "qgemm_last_invalid_arg": ([], _int),
     "qgemm_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
+    "qgemm_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
+    "qgemm_s_c64": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
 }
 
 
@@ -116,3 +118,23 @@ def qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None)
     rc = lib().qgemm_d(OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb, pb, _ptr(C), ldc,
                        _stream(stream))
     _raise(rc, "qgemm_d")
+
+
+def qgemm_s(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split_terms=6, stream=None):
+    """C <- alpha op(A) op(B) + beta C for FP32 storage, computed as split-BF16
+    products (split_terms in {3, 6, 9}) on the BF16 matrix cores with FP32
+    accumulation (C-ABI qgemm_s).  If C is float64 the result and the beta
+    term are formed in FP64 (C-ABI qgemm_s_c64)."""
+    ra, ca = _stored(opA, M, K)
+    rb, cb = _stored(opB, K, N)
+    if M and N and K:
+        _check_storage(A, ra, ca, lda, torch.float32, "A")
+        _check_storage(B, rb, cb, ldb, torch.float32, "B")
+    c64 = C is not None and C.dtype == torch.float64
+    _check_storage(C, M, N, ldc, torch.float64 if c64 else torch.float32, "C")
+    pa, _ka = _q4(alpha)
+    pb, _kb = _q4(beta)
+    fn = lib().qgemm_s_c64 if c64 else lib().qgemm_s
+    rc = fn(OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb, pb, _ptr(C), ldc, int(split_terms),
+            _stream(stream))
+    _raise(rc, "qgemm_s_c64" if c64 else "qgemm_s")

@@ -118,4 +118,34 @@ qgemm_status_t qgemm_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const 
     return QGEMM_OK;
 }
 
+static qgemm_status_t split_common(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+                                   const float *A, int64_t lda, const float *B, int64_t ldb, const double *beta,
+                                   float *C, double *C64, int64_t ldc, int split_terms, void *stream)
+{
+    const void *Cv = C64 ? static_cast<const void *>(C64) : static_cast<const void *>(C);
+    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, Cv, ldc, C64 ? 32 : 16);
+    if (s != QGEMM_OK) return s;
+    if (split_terms == 0) split_terms = 6;
+    if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 14);
+    if (M == 0 || N == 0) return QGEMM_OK;
+    auto d = make_desc<float>(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (qg::launch_qgemm_bf16x3(d, C64, split_terms, qg::kSplitPanel, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return QGEMM_ERR_HIP;
+    return QGEMM_OK;
+}
+
+qgemm_status_t qgemm_s(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+                       const float *A, int64_t lda, const float *B, int64_t ldb, const double *beta,
+                       float *C, int64_t ldc, int split_terms, void *stream)
+{
+    return split_common(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, nullptr, ldc, split_terms, stream);
+}
+
+qgemm_status_t qgemm_s_c64(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+                           const float *A, int64_t lda, const float *B, int64_t ldb, const double *beta,
+                           double *C, int64_t ldc, int split_terms, void *stream)
+{
+    return split_common(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, nullptr, C, ldc, split_terms, stream);
+}
+
 }  // extern "C"

@@ -32,6 +32,11 @@ struct GemmDesc {
 
 // Launch helpers (return a hipError_t from the launch).
 hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream);
+// Split-BF16 path for FP32 operands.  nterms in {3, 6, 9}; panel = kappa
+// length of the inner FP32 accumulation.  When c64 is non-null the result
+// (and the beta term) is written to that FP64 array instead of d.C.
+hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream);
+constexpr int kSplitPanel = 64;
 
 // 32-bit lane-constant sign mask of row r / column c of the real 4x4
 // left-multiplication block L(a) with vec(a b) = L(a) vec(b):
