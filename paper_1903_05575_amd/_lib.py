@@ -39,6 +39,10 @@ _SIGNATURES = {
     "qgemm_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemm_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
     "qgemm_s_c64": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
+    "qgemm_backward_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _dp,
+                          _vp, _i64, _vp, _i64, _vp, _i64, _vp], _int),
+    "qgemm_backward_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _dp,
+                          _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp], _int),
 }
 
 
@@ -138,3 +142,34 @@ def qgemm_s(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, split_terms=
     rc = fn(OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb, pb, _ptr(C), ldc, int(split_terms),
             _stream(stream))
     _raise(rc, "qgemm_s_c64" if c64 else "qgemm_s")
+
+
+def qgemm_backward(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta,
+                   dA=None, ldda=1, dB=None, lddb=1, dC0=None, lddc0=1, split_terms=6, stream=None):
+    """Gradients of <G, alpha op(A) op(B) + beta C0> with respect to the stored
+    A, B and C0, written (overwritten) into dA, dB, dC0 when given (C-ABI
+    qgemm_backward_d for float64 tensors, qgemm_backward_s for float32)."""
+    dtype = G.dtype
+    ra, ca = _stored(opA, M, K)
+    rb, cb = _stored(opB, K, N)
+    _check_storage(G, M, N, ldg, dtype, "G")
+    if dB is not None:
+        _check_storage(A, ra, ca, lda, dtype, "A")
+        _check_storage(dB, rb, cb, lddb, dtype, "dB")
+    if dA is not None:
+        _check_storage(B, rb, cb, ldb, dtype, "B")
+        _check_storage(dA, ra, ca, ldda, dtype, "dA")
+    if dC0 is not None:
+        _check_storage(dC0, M, N, lddc0, dtype, "dC0")
+    pa, _ka = _q4(alpha)
+    pb, _kb = _q4(beta)
+    args = [OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb, _ptr(G), ldg, pb,
+            _ptr(dA), ldda, _ptr(dB), lddb, _ptr(dC0), lddc0]
+    if dtype == torch.float64:
+        rc = lib().qgemm_backward_d(*args, _stream(stream))
+        _raise(rc, "qgemm_backward_d")
+    elif dtype == torch.float32:
+        rc = lib().qgemm_backward_s(*args, int(split_terms), _stream(stream))
+        _raise(rc, "qgemm_backward_s")
+    else:
+        raise ValueError(f"unsupported dtype {dtype}")

@@ -88,6 +88,104 @@ qg::GemmDesc<T> make_desc(int opA, int opB, int64_t M, int64_t N, int64_t K, con
     return d;
 }
 
+// op of the stored operand that yields op(X)^H, for the gradient:
+// N -> C, T -> R (conj only), C -> N, R -> T.
+int adjoint_op(int op)
+{
+    switch (op) {
+    case QGEMM_OP_N: return QGEMM_OP_C;
+    case QGEMM_OP_T: return QGEMM_OP_R;
+    case QGEMM_OP_C: return QGEMM_OP_N;
+    default: return QGEMM_OP_T;
+    }
+}
+
+// Gradient of L = <G, alpha op(A) op(B) + beta C0> (real inner product of the
+// components) with respect to the stored A, B and C0.  With the scalar
+// derivation of the oracle's header:
+//   d op(A) = conj(alpha) G op(B)^H                (left scalar)
+//   d op(B) = op(A)^H (conj(alpha) G)              (scalar between the factors)
+//   dC0     = conj(beta) G
+// and dX is d op(X) mapped back through op: N as is, T transposed, C
+// conjugate-transposed, R conjugated.  Each map is applied by the store of the
+// GEMM epilogue; the middle scalar is applied to op(B) as it is staged.
+template <typename T>
+qgemm_status_t backward_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha, const T *A,
+                             int64_t lda, const T *B, int64_t ldb, const T *G, int64_t ldg, const double *beta,
+                             T *dA, int64_t ldda, T *dB, int64_t lddb, T *dC0, int64_t lddc0, int split_terms,
+                             hipStream_t stream)
+{
+    constexpr uintptr_t align = 4 * sizeof(T);
+    g_bad_arg = 0;
+    if (!valid_op(opA)) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (!valid_op(opB)) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (M < 0) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (N < 0) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (K < 0) return fail(QGEMM_ERR_INVALID_ARG, 5);
+    if (M > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 3);
+    if (N > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 4);
+    if (K > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 5);
+    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    const int64_t rows_a = op_transposes(opA) ? K : M;
+    const int64_t rows_b = op_transposes(opB) ? N : K;
+    if (lda < (rows_a > 1 ? rows_a : 1)) return fail(QGEMM_ERR_INVALID_ARG, 8);
+    if (ldb < (rows_b > 1 ? rows_b : 1)) return fail(QGEMM_ERR_INVALID_ARG, 10);
+    if (ldg < (M > 1 ? M : 1)) return fail(QGEMM_ERR_INVALID_ARG, 12);
+    if (!beta) return fail(QGEMM_ERR_INVALID_ARG, 13);
+    if (dA && ldda < (rows_a > 1 ? rows_a : 1)) return fail(QGEMM_ERR_INVALID_ARG, 15);
+    if (dB && lddb < (rows_b > 1 ? rows_b : 1)) return fail(QGEMM_ERR_INVALID_ARG, 17);
+    if (dC0 && lddc0 < (M > 1 ? M : 1)) return fail(QGEMM_ERR_INVALID_ARG, 19);
+    if (split_terms == 0) split_terms = 6;
+    if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 20);
+    const bool need_a = dA && M > 0 && K > 0;
+    const bool need_b = dB && K > 0 && N > 0;
+    const bool need_c = dC0 && M > 0 && N > 0;
+    const bool reads_g = (need_a || need_b) ? (M > 0 && N > 0) : need_c;
+    if (reads_g && !G) return fail(QGEMM_ERR_INVALID_ARG, 11);
+    if (need_a && N > 0 && !B) return fail(QGEMM_ERR_INVALID_ARG, 9);
+    if (need_b && M > 0 && !A) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    auto misaligned = [&](const void *p) { return p && (reinterpret_cast<uintptr_t>(p) % align) != 0; };
+    if (misaligned(A)) return fail(QGEMM_ERR_MISALIGNED, 7);
+    if (misaligned(B)) return fail(QGEMM_ERR_MISALIGNED, 9);
+    if (misaligned(G)) return fail(QGEMM_ERR_MISALIGNED, 11);
+    if (misaligned(dA)) return fail(QGEMM_ERR_MISALIGNED, 14);
+    if (misaligned(dB)) return fail(QGEMM_ERR_MISALIGNED, 16);
+    if (misaligned(dC0)) return fail(QGEMM_ERR_MISALIGNED, 18);
+    if ((need_a && (dA == (const T *)A || dA == (const T *)B || dA == (const T *)G)) ||
+        (need_b && (dB == (const T *)A || dB == (const T *)B || dB == (const T *)G)))
+        return fail(QGEMM_ERR_INVALID_ARG, need_a ? 14 : 16);
+
+    const double one[4] = {1.0, 0.0, 0.0, 0.0};
+    const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+    const double ca[4] = {alpha[0], -alpha[1], -alpha[2], -alpha[3]};
+    auto launch = [&](qg::GemmDesc<T> &d) -> hipError_t {
+        if constexpr (sizeof(T) == 8) return qg::launch_qgemm_f64(d, stream);
+        else return qg::launch_qgemm_bf16x3(d, nullptr, split_terms, qg::kSplitPanel, stream);
+    };
+    if (need_a) {
+        // d op(A) (M x K) = conj(alpha) G (M x N) op(B)^H (N x K)
+        auto d = make_desc<T>(QGEMM_OP_N, adjoint_op(opB), M, K, N, ca, G, ldg, B, ldb, zero, dA, ldda);
+        d.store_t = op_transposes(opA);
+        d.store_conj = op_conjugates(opA);
+        if (launch(d) != hipSuccess) return QGEMM_ERR_HIP;
+    }
+    if (need_b) {
+        // d op(B) (K x N) = op(A)^H (K x M) (conj(alpha) G) (M x N)
+        auto d = make_desc<T>(adjoint_op(opA), QGEMM_OP_N, K, N, M, one, A, lda, G, ldg, zero, dB, lddb);
+        d.has_bscale = !(ca[0] == 1.0 && ca[1] == 0.0 && ca[2] == 0.0 && ca[3] == 0.0);
+        for (int i = 0; i < 4; ++i) d.bscale[i] = ca[i];
+        d.store_t = op_transposes(opB);
+        d.store_conj = op_conjugates(opB);
+        if (launch(d) != hipSuccess) return QGEMM_ERR_HIP;
+    }
+    if (need_c) {
+        const double cb[4] = {beta[0], -beta[1], -beta[2], -beta[3]};
+        if (qg::launch_scale_left<T>(G, ldg, dC0, lddc0, (int)M, (int)N, cb, stream) != hipSuccess)
+            return QGEMM_ERR_HIP;
+    }
+    return QGEMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -146,6 +244,24 @@ qgemm_status_t qgemm_s_c64(int opA, int opB, int64_t M, int64_t N, int64_t K, co
                            double *C, int64_t ldc, int split_terms, void *stream)
 {
     return split_common(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, nullptr, C, ldc, split_terms, stream);
+}
+
+qgemm_status_t qgemm_backward_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+                                const double *A, int64_t lda, const double *B, int64_t ldb, const double *G,
+                                int64_t ldg, const double *beta, double *dA, int64_t ldda, double *dB,
+                                int64_t lddb, double *dC0, int64_t lddc0, void *stream)
+{
+    return backward_impl<double>(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta, dA, ldda, dB, lddb, dC0,
+                                 lddc0, 6, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qgemm_backward_s(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+                                const float *A, int64_t lda, const float *B, int64_t ldb, const float *G,
+                                int64_t ldg, const double *beta, float *dA, int64_t ldda, float *dB, int64_t lddb,
+                                float *dC0, int64_t lddc0, int split_terms, void *stream)
+{
+    return backward_impl<float>(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta, dA, ldda, dB, lddb, dC0,
+                                lddc0, split_terms, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

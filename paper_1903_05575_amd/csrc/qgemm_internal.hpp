@@ -37,6 +37,10 @@ hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream);
 // (and the beta term) is written to that FP64 array instead of d.C.
 hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream);
 constexpr int kSplitPanel = 64;
+// Y <- s X elementwise (left scalar), M x N quaternions.
+template <typename T>
+hipError_t launch_scale_left(const T *X, int64_t ldx, T *Y, int64_t ldy, int M, int N, const double s[4],
+                             hipStream_t stream);
 
 // 32-bit lane-constant sign mask of row r / column c of the real 4x4
 // left-multiplication block L(a) with vec(a b) = L(a) vec(b):
