@@ -92,6 +92,118 @@ qgemm_status_t qgemm_d(int opA, int opB, int64_t M, int64_t N, int64_t K,
                        const double *B, int64_t ldb, const double *beta,
                        double *C, int64_t ldc, void *stream);
 
+/*
+ * qgemm_s -- FP32-stored quaternion GEMM as split-BF16 products on the BF16
+ * matrix cores with FP32 accumulation (an extension of the paper's FP64
+ * method, Sec. 4, to lower-precision matrix units).
+ * Computes C <- alpha op(A) op(B) + beta C with A, B, C device arrays of
+ * float.  Each FP32 component is split into three BF16 pieces (round to
+ * nearest even on successive residuals); split_terms selects the piece
+ * products formed: 3 (first order), 6 (default, all products down to 2^-16
+ * relative) or 9 (all); 0 means 6.  Accumulation is FP32 in two levels (an
+ * inner accumulator flushed every 64 quaternions of K).  alpha and beta are
+ * applied in FP32.  Inputs must be finite with |x| below the BF16 overflow
+ * threshold (about 3.39e38).
+ * Arguments: 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 alpha, 7 A, 8 lda, 9 B, 10 ldb,
+ *            11 beta, 12 C, 13 ldc, 14 split_terms, 15 stream.
+ */
+qgemm_status_t qgemm_s(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                       const double *alpha, const float *A, int64_t lda,
+                       const float *B, int64_t ldb, const double *beta,
+                       float *C, int64_t ldc, int split_terms, void *stream);
+
+/*
+ * qgemm_s_c64 -- as qgemm_s, but C is an array of double: the accumulated
+ * product is widened and alpha, beta and the update of C are done in FP64
+ * (for callers that keep the result in double).  C must be 32-byte aligned.
+ */
+qgemm_status_t qgemm_s_c64(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                           const double *alpha, const float *A, int64_t lda,
+                           const float *B, int64_t ldb, const double *beta,
+                           double *C, int64_t ldc, int split_terms, void *stream);
+
+/*
+ * Grouped (batched) FP32 quaternion GEMM: many independent problems
+ *   C_i <- alpha op(A_i) op(B_i) + beta C_i,  i = 0..count-1,
+ * with common ops, scalars and split, run as ONE persistent kernel launch
+ * of the split-BF16 path.  This batching is an extension beyond the paper;
+ * the tile shape of each problem is chosen per size class from a table
+ * produced by the library's tile tuner (the analogue of the paper's
+ * autotuned caching parameters, Sec. 5).
+ *
+ * qgemm_batched_plan_create: validates every problem (as qgemm_s does;
+ *   on failure qgemm_last_invalid_arg() names the field -- 3 M, 4 N, 5 K,
+ *   7 A, 8 lda, 9 B, 10 ldb, 12 C, 13 ldc -- and qgemm_last_invalid_problem()
+ *   its index), builds the work table on the host and copies it to the
+ *   current device (hipMalloc + synchronous copy: do NOT call it inside a
+ *   stream capture).  tile_class < 0 uses the tuned table; 0..4 forces one
+ *   class (0 = 64x64, 1 = 32x64, 2 = 64x32, 3 = 32x32, 4 = 16x64
+ *   quaternions) for every problem.  The plan keeps the problem pointers and
+ *   sizes: the buffers must stay valid while the plan is run.
+ *   Arguments: 1 plan, 2 opA, 3 opB, 4 count, 5 problems, 6 alpha, 7 beta,
+ *   8 split_terms, 9 tile_class.
+ * qgemm_batched_run: enqueues the single launch on `stream`.  It allocates
+ *   nothing, copies nothing and does not synchronise, so it may be captured
+ *   into a hipGraph and replayed.  Must run on the device the plan was made
+ *   on.  Problems whose C overlap, or overlap any A or B, give undefined
+ *   results.
+ * qgemm_batched_plan_destroy: frees the plan's device tables (synchronises
+ *   the device).
+ */
+typedef struct qgemm_problem_t {
+    int64_t M, N, K;
+    int64_t lda, ldb, ldc;
+    const void *A;
+    const void *B;
+    void *C;
+} qgemm_problem_t;
+
+typedef struct qgemm_plan_s *qgemm_plan_t;
+
+qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, int64_t count,
+                                         const qgemm_problem_t *problems, const double *alpha,
+                                         const double *beta, int split_terms, int tile_class);
+qgemm_status_t qgemm_batched_run(qgemm_plan_t plan, void *stream);
+qgemm_status_t qgemm_batched_plan_destroy(qgemm_plan_t plan);
+/* Work items, grid size and tiles per class (array of 5) of a plan. */
+qgemm_status_t qgemm_batched_plan_info(qgemm_plan_t plan, int64_t *work_items, int *grid,
+                                       int64_t *class_counts);
+/* Index of the problem that made the last plan creation on this thread fail, or -1. */
+int64_t qgemm_last_invalid_problem(void);
+
+/*
+ * Gradient of the real loss L = sum_{mu,nu} <G_{mu nu}, C_{mu nu}> (the
+ * Euclidean inner product of the four components) for
+ *     C = alpha op(A) op(B) + beta C0,
+ * with respect to the stored A, B and C0 (an extension beyond the paper):
+ *     d op(A) = conj(alpha) G op(B)^H,   d op(B) = op(A)^H (conj(alpha) G),
+ *     dC0 = conj(beta) G,
+ * mapped back through op (N: as is, T: transposed, C: conjugate-transposed,
+ * R: conjugated).  dA (stored like A, leading dimension ldda), dB (like B,
+ * lddb) and dC0 (M x N, lddc0) are overwritten; any of them may be NULL to
+ * skip it.  G is M x N with leading dimension ldg.  alpha and beta are
+ * constants (no gradient).  At most two GEMM launches and one elementwise
+ * launch are enqueued; no workspace is allocated.
+ * qgemm_backward_d runs in FP64; qgemm_backward_s on FP32 data through the
+ * split-BF16 path (split_terms as in qgemm_s).
+ * Arguments: 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 alpha, 7 A, 8 lda, 9 B, 10 ldb,
+ *   11 G, 12 ldg, 13 beta, 14 dA, 15 ldda, 16 dB, 17 lddb, 18 dC0, 19 lddc0,
+ *   20 split_terms (qgemm_backward_s only), then stream.
+ * Outputs must not overlap the inputs.
+ */
+qgemm_status_t qgemm_backward_d(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                                const double *alpha, const double *A, int64_t lda,
+                                const double *B, int64_t ldb, const double *G, int64_t ldg,
+                                const double *beta, double *dA, int64_t ldda,
+                                double *dB, int64_t lddb, double *dC0, int64_t lddc0,
+                                void *stream);
+qgemm_status_t qgemm_backward_s(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                                const double *alpha, const float *A, int64_t lda,
+                                const float *B, int64_t ldb, const float *G, int64_t ldg,
+                                const double *beta, float *dA, int64_t ldda,
+                                float *dB, int64_t lddb, float *dC0, int64_t lddc0,
+                                int split_terms, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,12 +33,25 @@ _int = ctypes.c_int
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 
+class Problem(ctypes.Structure):
+    """Mirror of qgemm_problem_t (include/qgemm.h)."""
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p)]
+
+
 _SIGNATURES = {
     "qgemm_status_string": ([_int], ctypes.c_char_p),
     "qgemm_last_invalid_arg": ([], _int),
     "qgemm_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemm_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
     "qgemm_s_c64": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
+    "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
+                                   _int, _int], _int),
+    "qgemm_batched_run": ([_vp, _vp], _int),
+    "qgemm_batched_plan_destroy": ([_vp], _int),
+    "qgemm_batched_plan_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_int), ctypes.POINTER(_i64)], _int),
+    "qgemm_last_invalid_problem": ([], _i64),
     "qgemm_backward_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _dp,
                           _vp, _i64, _vp, _i64, _vp, _i64, _vp], _int),
     "qgemm_backward_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _dp,
@@ -173,3 +186,68 @@ def qgemm_backward(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta,
         _raise(rc, "qgemm_backward_s")
     else:
         raise ValueError(f"unsupported dtype {dtype}")
+
+
+TILE_CLASSES = ((64, 64), (32, 64), (64, 32), (32, 32), (16, 64))
+
+
+class GroupedPlan:
+    """A grouped (batched) FP32 quaternion GEMM plan (C-ABI
+    qgemm_batched_plan_create / _run / _plan_destroy).
+
+    problems: sequence of dicts with float32 GPU tensors A, B, C and the ints
+    M, N, K, lda, ldb, ldc.  The tensors must outlive the plan; the plan keeps
+    references to them.  run() enqueues one persistent launch on the current
+    (or given) stream and may be captured in a CUDA/HIP graph."""
+
+    def __init__(self, problems, opA="N", opB="N", alpha=(1, 0, 0, 0), beta=(0, 0, 0, 0), split_terms=6,
+                 tile_class=-1):
+        self._handle = None
+        self._keep = []
+        arr = (Problem * max(1, len(problems)))()
+        for i, pr in enumerate(problems):
+            M, N, K = pr["M"], pr["N"], pr["K"]
+            ra, ca = _stored(opA, M, K)
+            rb, cb = _stored(opB, K, N)
+            if M and N and K:
+                _check_storage(pr["A"], ra, ca, pr["lda"], torch.float32, f"problems[{i}].A")
+                _check_storage(pr["B"], rb, cb, pr["ldb"], torch.float32, f"problems[{i}].B")
+            _check_storage(pr["C"], M, N, pr["ldc"], torch.float32, f"problems[{i}].C")
+            arr[i] = Problem(M, N, K, pr["lda"], pr["ldb"], pr["ldc"],
+                             pr["A"].data_ptr() if pr.get("A") is not None else None,
+                             pr["B"].data_ptr() if pr.get("B") is not None else None,
+                             pr["C"].data_ptr() if pr.get("C") is not None else None)
+            self._keep.append((pr.get("A"), pr.get("B"), pr.get("C")))
+        pa, _ka = _q4(alpha)
+        pb, _kb = _q4(beta)
+        h = ctypes.c_void_p()
+        rc = lib().qgemm_batched_plan_create(ctypes.byref(h), OPS[opA], OPS[opB], len(problems), arr, pa, pb,
+                                             int(split_terms), int(tile_class))
+        if rc != 0:
+            bad = lib().qgemm_last_invalid_problem()
+            raise QGemmError(rc, lib().qgemm_last_invalid_arg(), f"qgemm_batched_plan_create (problem {bad})")
+        self._handle = h
+
+    def run(self, stream=None):
+        rc = lib().qgemm_batched_run(self._handle, _stream(stream))
+        _raise(rc, "qgemm_batched_run")
+
+    def info(self):
+        n = ctypes.c_int64()
+        g = ctypes.c_int()
+        cls = (ctypes.c_int64 * len(TILE_CLASSES))()
+        _raise(lib().qgemm_batched_plan_info(self._handle, ctypes.byref(n), ctypes.byref(g), cls),
+               "qgemm_batched_plan_info")
+        return {"work_items": n.value, "grid": g.value, "tiles_per_class": list(cls)}
+
+    def close(self):
+        if self._handle is not None:
+            lib().qgemm_batched_plan_destroy(self._handle)
+            self._handle = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,9 +6,12 @@
 
 #include <stdint.h>
 
+#include <new>
+
 namespace {
 
 thread_local int g_bad_arg = 0;
+thread_local int64_t g_bad_problem = -1;
 
 qgemm_status_t fail(qgemm_status_t s, int arg)
 {
@@ -262,6 +265,73 @@ qgemm_status_t qgemm_backward_s(int opA, int opB, int64_t M, int64_t N, int64_t 
 {
     return backward_impl<float>(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta, dA, ldda, dB, lddb, dC0,
                                 lddc0, split_terms, static_cast<hipStream_t>(stream));
+}
+
+int64_t qgemm_last_invalid_problem(void) { return g_bad_problem; }
+
+struct qgemm_plan_s {
+    qg::GroupedPlan *impl;
+};
+
+qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, int64_t count,
+                                         const qgemm_problem_t *problems, const double *alpha,
+                                         const double *beta, int split_terms, int tile_class)
+{
+    g_bad_arg = 0;
+    g_bad_problem = -1;
+    if (!plan) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    *plan = nullptr;
+    if (!valid_op(opA)) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (!valid_op(opB)) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (count < 0 || count > kMaxDim) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (count > 0 && !problems) return fail(QGEMM_ERR_INVALID_ARG, 5);
+    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (!beta) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    if (split_terms == 0) split_terms = 6;
+    if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 8);
+    if (tile_class >= qg::kGroupedClasses) return fail(QGEMM_ERR_INVALID_ARG, 9);
+    for (int64_t i = 0; i < count; ++i) {
+        const qgemm_problem_t &q = problems[i];
+        qgemm_status_t s = validate(opA, opB, q.M, q.N, q.K, alpha, q.A, q.lda, q.B, q.ldb, beta, q.C, q.ldc, 16);
+        if (s != QGEMM_OK) {
+            g_bad_problem = i;
+            return s;
+        }
+    }
+    qg::GroupedPlan *impl = nullptr;
+    int rc = qg::grouped_plan_create(&impl, op_transposes(opA), op_transposes(opB), op_conjugates(opA),
+                                     op_conjugates(opB), split_terms, alpha, beta, count, problems, tile_class);
+    if (rc != QGEMM_OK) return (qgemm_status_t)rc;
+    qgemm_plan_s *h = new (std::nothrow) qgemm_plan_s{impl};
+    if (!h) {
+        qg::grouped_plan_destroy(impl);
+        return QGEMM_ERR_ALLOC;
+    }
+    *plan = h;
+    return QGEMM_OK;
+}
+
+qgemm_status_t qgemm_batched_run(qgemm_plan_t plan, void *stream)
+{
+    g_bad_arg = 0;
+    if (!plan || !plan->impl) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    return (qgemm_status_t)qg::grouped_plan_run(plan->impl, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qgemm_batched_plan_destroy(qgemm_plan_t plan)
+{
+    if (!plan) return QGEMM_OK;
+    qg::grouped_plan_destroy(plan->impl);
+    delete plan;
+    return QGEMM_OK;
+}
+
+qgemm_status_t qgemm_batched_plan_info(qgemm_plan_t plan, int64_t *work_items, int *grid, int64_t *class_counts)
+{
+    g_bad_arg = 0;
+    if (!plan || !plan->impl) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    qg::grouped_plan_info(plan->impl, work_items, grid, class_counts);
+    return QGEMM_OK;
 }
 
 }  // extern "C"

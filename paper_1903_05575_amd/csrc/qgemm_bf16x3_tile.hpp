@@ -1,0 +1,360 @@
+// One output tile of the FP32-stored quaternion GEMM computed as split-BF16
+// products on the gfx950 BF16 matrix cores (FP32 accumulation).  Shared by
+// the single-GEMM kernel and the grouped (batched) kernel.
+//
+// Split.  While a tile is staged from HBM into LDS every FP32 component x is
+// split into three BF16 pieces with round-to-nearest-even on the successive
+// residuals:  h = bf16(x), m = bf16(x - h), l = bf16(x - h - m).  Both
+// residuals are exact in FP32, and h + m + l == x for finite |x| below the
+// BF16 overflow threshold.  A product a b is the sum of the nine piece
+// products; NTERMS selects how many are formed, in order of magnitude:
+//   3: hh hm mh      6: + hl mm lh (all terms down to 2^-16 relative)
+//   9: + ml lm ll (exact up to accumulation rounding)
+//
+// Quaternion structure.  As in the FP64 path the product is the real GEMM
+// C_real (4M x N) = L(op A) (4M x 4K) B_real (4K x N), where L(a) is the 4x4
+// left-multiplication block of a (derived from Eq. quaternion_prod).  The
+// BF16 A operand is formed from LDS by a byte permutation and a sign XOR per
+// register: no extra HBM traffic, no flops.
+//
+// MFMA.  v_mfma_f32_32x32x16_bf16: A 32 x 16 (lane l: row l % 32, eight k
+// values of group l / 32), B 16 x 32 (lane l: column l % 32, the same eight k
+// slots), D 32 x 32 with D[i][j] in lane j + 32 ((i / 4) % 2), register
+// 4 (i / 8) + i % 4 (layout measured on gfx950).  Row i of A is quaternion row
+// i / 4, component i % 4; the eight k slots of group g are quaternions
+// 2g, 2g + 1 of the 4-kappa step, components 0..3.  Then every lane holds
+// four complete output quaternions (registers 4j..4j+3), and a B fragment is
+// two consecutive quaternions of one column: one 16-byte LDS read.  One MFMA
+// block is 8 quaternion rows x 32 quaternion columns x 4 kappa.
+//
+// Accumulation.  One FP32 MFMA accumulator per output takes all NTERMS
+// products; every `panel_tiles` K-tiles it is added into a second FP32
+// accumulator and cleared, so rounding errors grow with the panel length
+// rather than with K.
+//
+// Tile.  A block of 256 threads (4 waves, arranged WR x WC) computes BM x BN
+// quaternions; a wave owns (BM/WR) x (BN/WC) = MB x NB MFMA blocks.  K
+// advances in tiles of BK quaternions through two LDS stages (the next tile is
+// fetched into registers while the current one is multiplied).
+// LDS (32-bit words): per stage, A as [piece][row][kappa][2 words] and B as
+// [piece][column][kappa][2 words], row pitch 2 BK + 4 words.  The 16-byte pad
+// spreads the 16-byte fragment reads of consecutive rows over the banks.
+#pragma once
+
+#include "qgemm_internal.hpp"
+
+namespace qg {
+namespace split {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;
+
+// f32 pair -> packed bf16 pair (round to nearest even), low half = first
+__device__ __forceinline__ unsigned pack_bf16(float x, float y)
+{
+    const bf16x2 v = __builtin_convertvector((f32x2){x, y}, bf16x2);
+    return __builtin_bit_cast(unsigned, v);
+}
+__device__ __forceinline__ float lo_f32(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_f32(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Split two floats into three packed bf16 pairs (h, m, l).
+__device__ __forceinline__ void split2(float x, float y, unsigned &h, unsigned &m, unsigned &l)
+{
+    h = pack_bf16(x, y);
+    const float rx = x - lo_f32(h), ry = y - hi_f32(h);
+    m = pack_bf16(rx, ry);
+    const float sx = rx - lo_f32(m), sy = ry - hi_f32(m);
+    l = pack_bf16(sx, sy);
+}
+
+// Row r of L(a) for one quaternion a held as two packed bf16 words
+// w0 = (a0, a1), w1 = (a2, a3):
+//   r = 0: ( a0, -a1, -a2, -a3)     r = 1: ( a1,  a0, -a3,  a2)
+//   r = 2: ( a2,  a3,  a0, -a1)     r = 3: ( a3, -a2,  a1,  a0)
+// Each output word is one byte permutation of (w1:w0) and one sign XOR.
+struct LRow {
+    unsigned sel0, sel1, neg0, neg1;
+};
+__device__ __forceinline__ LRow lrow(int r)
+{
+    // v_perm selectors over the 8 bytes {w1, w0}: bytes 0-3 = w0, 4-7 = w1
+    constexpr unsigned P01 = 0x03020100u, P10 = 0x01000302u, P23 = 0x07060504u, P32 = 0x05040706u;
+    LRow x;
+    x.sel0 = r == 0 ? P01 : r == 1 ? P10 : r == 2 ? P23 : P32;
+    x.sel1 = r == 0 ? P23 : r == 1 ? P32 : r == 2 ? P01 : P10;
+    x.neg0 = (r == 0 || r == 3) ? 0x80000000u : 0u;
+    x.neg1 = r == 0 ? 0x80008000u : r == 1 ? 0x00008000u : r == 2 ? 0x80000000u : 0u;
+    return x;
+}
+
+__device__ __forceinline__ bf16x8 expand_a(u32x4 raw, const LRow &L)
+{
+    u32x4 o;
+    o.x = __builtin_amdgcn_perm(raw.y, raw.x, L.sel0) ^ L.neg0;
+    o.y = __builtin_amdgcn_perm(raw.y, raw.x, L.sel1) ^ L.neg1;
+    o.z = __builtin_amdgcn_perm(raw.w, raw.z, L.sel0) ^ L.neg0;
+    o.w = __builtin_amdgcn_perm(raw.w, raw.z, L.sel1) ^ L.neg1;
+    return __builtin_bit_cast(bf16x8, o);
+}
+
+// (A piece, B piece) of each product, smallest first so that the large term
+// lands on an accumulator already holding the corrections.
+template <int NTERMS>
+struct Terms;
+template <>
+struct Terms<3> {
+    static constexpr int n = 3;
+    static constexpr int a[3] = {1, 0, 0};
+    static constexpr int b[3] = {0, 1, 0};
+};
+template <>
+struct Terms<6> {
+    static constexpr int n = 6;
+    static constexpr int a[6] = {2, 1, 0, 1, 0, 0};
+    static constexpr int b[6] = {0, 1, 2, 0, 1, 0};
+};
+template <>
+struct Terms<9> {
+    static constexpr int n = 9;
+    static constexpr int a[9] = {2, 2, 1, 2, 1, 0, 1, 0, 0};
+    static constexpr int b[9] = {2, 1, 2, 0, 1, 2, 0, 1, 0};
+};
+
+template <int BM_, int BN_, int WR_, int WC_, int BK_>
+struct Tile {
+    static constexpr int BM = BM_, BN = BN_, WR = WR_, WC = WC_, BK = BK_;
+    static constexpr int MB = BM / WR / 8;                     // MFMA blocks per wave along M
+    static constexpr int NB = BN / WC / 32;                    // MFMA blocks per wave along N
+    static constexpr int RP = 2 * BK + 4;                      // words per LDS row (incl. 16-byte pad)
+    static constexpr int A_STAGE = 3 * BM * RP;
+    static constexpr int B_STAGE = 3 * BN * RP;
+    static constexpr int STAGE = A_STAGE + B_STAGE;
+    static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(unsigned);
+    static constexpr int A_Q = BM * BK / NT;                   // quaternions of A per thread per K-tile
+    static constexpr int B_Q = BN * BK / NT;
+    static_assert(WR * WC == 4, "four waves per block");
+    static_assert(MB >= 1 && NB >= 1 && MB * WR * 8 == BM && NB * WC * 32 == BN, "wave tiling");
+    static_assert(A_Q >= 1 && B_Q >= 1 && A_Q * NT == BM * BK && B_Q * NT == BN * BK, "tile split");
+    static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA kappa step");
+};
+
+// Compute the BM x BN output tile at (m0, n0) of problem p and write it.
+// nk = number of K-tiles to walk (0 when alpha == 0).  `lds` must hold
+// Tile::LDS_BYTES.  Every thread of the block must call this.
+template <class TL, bool TA, bool TB, int NTERMS, bool C64>
+__device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64, int m0, int n0, int nk,
+                                           int panel_tiles, unsigned *lds)
+{
+    using TT = Terms<NTERMS>;
+    constexpr int BM = TL::BM, BN = TL::BN, BK = TL::BK, MB = TL::MB, NB = TL::NB, RP = TL::RP;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr = wave / TL::WC, wc = wave % TL::WC;
+
+    const int fi = lane & 31;                 // A row / B column within the 32-wide MFMA block
+    const int fg = lane >> 5;                 // k group: quaternions 2fg, 2fg+1 of the step
+    const LRow L = lrow(fi & 3);
+    const int a_row = wr * (BM / TL::WR) + (fi >> 2);   // + 8 m
+    const int b_row = wc * (BN / TL::WC) + fi;          // + 32 n
+
+    f32x16 acc[MB][NB], tot[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            acc[m][n] = (f32x16){};
+            tot[m][n] = (f32x16){};
+        }
+
+    f32x4 ra[TL::A_Q], rb[TL::B_Q];
+
+    auto a_coords = [&](int i, int &row, int &ka) {
+        const int qd = tid + NT * i;
+        if (!TA) { row = qd % BM; ka = qd / BM; }     // stored contiguous along mu
+        else     { ka = qd % BK; row = qd / BK; }     // stored contiguous along kappa
+    };
+    auto b_coords = [&](int i, int &col, int &ka) {
+        const int qd = tid + NT * i;
+        if (!TB) { ka = qd % BK; col = qd / BK; }
+        else     { col = qd % BN; ka = qd / BN; }
+    };
+
+    auto load_tile = [&](int kt) {
+        const int k0 = kt * BK;
+#pragma unroll
+        for (int i = 0; i < TL::A_Q; ++i) {
+            int row, ka;
+            a_coords(i, row, ka);
+            const int gm = m0 + row, gk = k0 + ka;
+            if (gm < p.M && gk < p.K) {
+                const int64_t e = TA ? ((int64_t)gm * p.lda + gk) : ((int64_t)gk * p.lda + gm);
+                ra[i] = *reinterpret_cast<const f32x4 *>(p.A + 4 * e);
+            } else {
+                ra[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < TL::B_Q; ++i) {
+            int col, ka;
+            b_coords(i, col, ka);
+            const int gn = n0 + col, gk = k0 + ka;
+            if (gn < p.N && gk < p.K) {
+                const int64_t e = TB ? ((int64_t)gk * p.ldb + gn) : ((int64_t)gn * p.ldb + gk);
+                rb[i] = *reinterpret_cast<const f32x4 *>(p.B + 4 * e);
+            } else {
+                rb[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    };
+
+    auto put = [&](unsigned *plane0, int plane_words, int row, int ka, f32x4 v) {
+        unsigned h0, md0, l0, h1, md1, l1;
+        split2(v.x, v.y, h0, md0, l0);
+        split2(v.z, v.w, h1, md1, l1);
+        unsigned *d = plane0 + row * RP + 2 * ka;
+        *reinterpret_cast<uint2 *>(d) = make_uint2(h0, h1);
+        *reinterpret_cast<uint2 *>(d + plane_words) = make_uint2(md0, md1);
+        *reinterpret_cast<uint2 *>(d + 2 * plane_words) = make_uint2(l0, l1);
+    };
+
+    auto store_tile = [&](int stage) {
+        unsigned *As = lds + stage * TL::STAGE;
+        unsigned *Bs = As + TL::A_STAGE;
+#pragma unroll
+        for (int i = 0; i < TL::A_Q; ++i) {
+            int row, ka;
+            a_coords(i, row, ka);
+            f32x4 v = ra[i];
+            if (p.conjA) { v.y = -v.y; v.z = -v.z; v.w = -v.w; }
+            put(As, BM * RP, row, ka, v);
+        }
+#pragma unroll
+        for (int i = 0; i < TL::B_Q; ++i) {
+            int col, ka;
+            b_coords(i, col, ka);
+            f32x4 v = rb[i];
+            if (p.conjB) { v.y = -v.y; v.z = -v.z; v.w = -v.w; }
+            if (p.has_bscale) {
+                const float s[4] = {(float)p.bscale[0], (float)p.bscale[1], (float)p.bscale[2], (float)p.bscale[3]};
+                const float b[4] = {v.x, v.y, v.z, v.w};
+                float t[4];
+                qmul(s, b, t);
+                v = (f32x4){t[0], t[1], t[2], t[3]};
+            }
+            put(Bs, BN * RP, col, ka, v);
+        }
+    };
+
+    auto compute = [&](int stage) {
+        const unsigned *As = lds + stage * TL::STAGE;
+        const unsigned *Bs = As + TL::A_STAGE;
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kw = (ks * 4 + 2 * fg) * 2;          // word offset of the kappa pair
+            bf16x8 af[3][MB], bfr[3][NB];
+#pragma unroll
+            for (int pc = 0; pc < 3; ++pc) {
+#pragma unroll
+                for (int m = 0; m < MB; ++m) {
+                    const u32x4 raw = *reinterpret_cast<const u32x4 *>(As + (pc * BM + a_row + 8 * m) * RP + kw);
+                    af[pc][m] = expand_a(raw, L);
+                }
+#pragma unroll
+                for (int n = 0; n < NB; ++n) {
+                    const u32x4 raw = *reinterpret_cast<const u32x4 *>(Bs + (pc * BN + b_row + 32 * n) * RP + kw);
+                    bfr[pc][n] = __builtin_bit_cast(bf16x8, raw);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < TT::n; ++t)
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[TT::a[t]][m], bfr[TT::b[t]][n],
+                                                                            acc[m][n], 0, 0, 0);
+        }
+    };
+
+    auto flush = [&]() {
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                tot[m][n] += acc[m][n];
+                acc[m][n] = (f32x16){};
+            }
+    };
+
+    if (nk > 0) {
+        load_tile(0);
+        store_tile(0);
+        __syncthreads();
+    }
+    for (int kt = 0; kt < nk; ++kt) {
+        const int stage = kt & 1;
+        if (kt + 1 < nk) load_tile(kt + 1);
+        compute(stage);
+        if ((kt + 1) % panel_tiles == 0) flush();
+        if (kt + 1 < nk) store_tile(stage ^ 1);
+        __syncthreads();
+    }
+    flush();
+
+    // epilogue: a lane holds quaternions (registers 4j..4j+3) of rows 2j + lane/32 of each 8-row block
+    const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int mu = m0 + a_row - (fi >> 2) + 8 * m + 2 * j + fg;
+                const int nu = n0 + b_row + 32 * n;
+                if (mu >= p.M || nu >= p.N) continue;
+                const int64_t e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
+                if constexpr (C64) {
+                    const double v[4] = {tot[m][n][4 * j], tot[m][n][4 * j + 1], tot[m][n][4 * j + 2],
+                                         tot[m][n][4 * j + 3]};
+                    double o[4];
+                    qmul(p.alpha, v, o);
+                    if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
+                    double *dst = c64 + 4 * e;
+                    if (!beta_zero) {
+                        const double cq[4] = {dst[0], dst[1], dst[2], dst[3]};
+                        double u[4];
+                        qmul(p.beta, cq, u);
+                        o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
+                    }
+                    dst[0] = o[0]; dst[1] = o[1]; dst[2] = o[2]; dst[3] = o[3];
+                } else {
+                    const float al[4] = {(float)p.alpha[0], (float)p.alpha[1], (float)p.alpha[2], (float)p.alpha[3]};
+                    const float v[4] = {tot[m][n][4 * j], tot[m][n][4 * j + 1], tot[m][n][4 * j + 2],
+                                        tot[m][n][4 * j + 3]};
+                    float o[4];
+                    qmul(al, v, o);
+                    if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
+                    f32x4 *dst = reinterpret_cast<f32x4 *>(p.C + 4 * e);
+                    if (!beta_zero) {
+                        const float be[4] = {(float)p.beta[0], (float)p.beta[1], (float)p.beta[2], (float)p.beta[3]};
+                        const f32x4 c = *dst;
+                        const float cq[4] = {c.x, c.y, c.z, c.w};
+                        float u[4];
+                        qmul(be, cq, u);
+                        o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
+                    }
+                    *dst = (f32x4){o[0], o[1], o[2], o[3]};
+                }
+            }
+}
+
+}  // namespace split
+}  // namespace qg

@@ -1,0 +1,289 @@
+// Grouped (batched) FP32 quaternion GEMM: thousands of independent problems
+// of uneven size in one persistent launch of the split-BF16 tile.
+//
+// Plan (host, outside any capture): every problem is cut into output tiles
+// whose shape is looked up per size class in the tuned tile table
+// (tile_table.inc); the (problem, tile) work items are sorted by cost
+// (padded MFMA work + a fixed per-tile overhead) and dealt to the persistent
+// blocks longest-processing-time first, each block receiving a contiguous
+// run of the item array.  Problem descriptors, items and per-block offsets
+// go to device memory once.
+// Run (capture-safe): a single launch of one block per CU; block b walks
+// items [start[b], start[b+1]).  No allocation, copy, memset or atomic.
+#include "qgemm_bf16x3_tile.hpp"
+
+#include "../../include/qgemm.h"
+
+#include <algorithm>
+#include <functional>
+#include <new>
+#include <numeric>
+#include <queue>
+#include <vector>
+
+namespace qg {
+namespace {
+
+#include "tile_table.inc"
+
+struct DevProblem {
+    const float *A;
+    const float *B;
+    float *C;
+    int64_t lda, ldb, ldc;
+    int M, N, K, pad;
+};
+
+using T0 = split::Tile<64, 64, 4, 1, 16>;
+using T1 = split::Tile<32, 64, 4, 1, 16>;
+using T2 = split::Tile<64, 32, 4, 1, 16>;
+using T3 = split::Tile<32, 32, 4, 1, 16>;
+using T4 = split::Tile<16, 64, 2, 2, 16>;
+constexpr int kClasses = 5;
+constexpr int kBM[kClasses] = {64, 32, 64, 32, 16};
+constexpr int kBN[kClasses] = {64, 64, 32, 32, 64};
+constexpr int kBK = 16;
+constexpr size_t kLds = T0::LDS_BYTES;   // the largest of the classes
+static_assert(T1::LDS_BYTES <= kLds && T2::LDS_BYTES <= kLds && T3::LDS_BYTES <= kLds && T4::LDS_BYTES <= kLds,
+              "LDS sized for the largest tile");
+
+struct Scalars {
+    double alpha[4];
+    double beta[4];
+    int conjA, conjB;
+};
+
+template <bool TA, bool TB, int NTERMS>
+__global__ __launch_bounds__(split::NT, 1) void grouped_kernel(const DevProblem *__restrict__ probs,
+                                                             const int4 *__restrict__ items,
+                                                             const int *__restrict__ starts, Scalars s,
+                                                             int panel_tiles)
+{
+    extern __shared__ unsigned lds[];
+    const bool alpha_zero = s.alpha[0] == 0.0 && s.alpha[1] == 0.0 && s.alpha[2] == 0.0 && s.alpha[3] == 0.0;
+    const int end = starts[blockIdx.x + 1];
+    for (int w = starts[blockIdx.x]; w < end; ++w) {
+        const int4 it = items[w];                       // (problem, tile row, tile column, class)
+        const DevProblem pr = probs[it.x];
+        GemmDesc<float> d;
+        d.A = pr.A;
+        d.B = pr.B;
+        d.C = pr.C;
+        d.lda = pr.lda;
+        d.ldb = pr.ldb;
+        d.ldc = pr.ldc;
+        d.M = pr.M;
+        d.N = pr.N;
+        d.K = pr.K;
+        d.opA_t = TA;
+        d.opB_t = TB;
+        d.conjA = s.conjA != 0;
+        d.conjB = s.conjB != 0;
+        d.has_bscale = false;
+        d.store_t = false;
+        d.store_conj = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            d.alpha[i] = s.alpha[i];
+            d.beta[i] = s.beta[i];
+            d.bscale[i] = 0.0;
+        }
+        const int nk = alpha_zero ? 0 : (pr.K + kBK - 1) / kBK;
+        switch (it.w) {
+        case 0: split::split_tile<T0, TA, TB, NTERMS, false>(d, nullptr, it.y * 64, it.z * 64, nk, panel_tiles, lds); break;
+        case 1: split::split_tile<T1, TA, TB, NTERMS, false>(d, nullptr, it.y * 32, it.z * 64, nk, panel_tiles, lds); break;
+        case 2: split::split_tile<T2, TA, TB, NTERMS, false>(d, nullptr, it.y * 64, it.z * 32, nk, panel_tiles, lds); break;
+        case 3: split::split_tile<T3, TA, TB, NTERMS, false>(d, nullptr, it.y * 32, it.z * 32, nk, panel_tiles, lds); break;
+        default: split::split_tile<T4, TA, TB, NTERMS, false>(d, nullptr, it.y * 16, it.z * 64, nk, panel_tiles, lds); break;
+        }
+        __syncthreads();                                 // LDS is reused by the next item
+    }
+}
+
+int bucket_mn(int64_t x) { return x <= 16 ? 0 : x <= 32 ? 1 : x <= 64 ? 2 : 3; }
+int bucket_k(int64_t x) { return x <= 64 ? 0 : 1; }
+
+template <bool TA, bool TB, int NTERMS>
+hipError_t set_attr()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&grouped_kernel<TA, TB, NTERMS>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+template <int NTERMS>
+hipError_t launch_n(bool ta, bool tb, dim3 grid, hipStream_t st, const DevProblem *p, const int4 *it,
+                    const int *starts, Scalars s, int panel_tiles)
+{
+#define QG_GROUPED_CASE(A_, B_)                                                                         \
+    if (ta == A_ && tb == B_) {                                                                         \
+        hipError_t e = set_attr<A_, B_, NTERMS>();                                                      \
+        if (e != hipSuccess) return e;                                                                  \
+        hipLaunchKernelGGL((grouped_kernel<A_, B_, NTERMS>), grid, dim3(split::NT), kLds, st, p, it, starts, s, \
+                           panel_tiles);                                                                \
+        return hipGetLastError();                                                                       \
+    }
+    QG_GROUPED_CASE(false, false)
+    QG_GROUPED_CASE(false, true)
+    QG_GROUPED_CASE(true, false)
+    QG_GROUPED_CASE(true, true)
+#undef QG_GROUPED_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+struct GroupedPlan {
+    int device = 0;
+    bool ta = false, tb = false;
+    int nterms = 6;
+    Scalars s{};
+    DevProblem *d_probs = nullptr;
+    int4 *d_items = nullptr;
+    int *d_starts = nullptr;
+    int64_t nitems = 0;
+    int grid = 0;
+    int64_t class_count[kClasses] = {};
+};
+
+int grouped_tile_class(int64_t M, int64_t N, int64_t K) { return kTileTable[bucket_mn(M)][bucket_mn(N)][bucket_k(K)]; }
+
+// Build a plan.  `probs` have been validated by the caller.  force_class < 0
+// selects the tile class from the table, otherwise it is used for every
+// problem.  Returns QGEMM_OK, QGEMM_ERR_ALLOC or QGEMM_ERR_HIP.
+int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, int nterms, const double alpha[4],
+                        const double beta[4], int64_t count, const ::qgemm_problem_t *probs, int force_class)
+{
+    GroupedPlan *pl = new (std::nothrow) GroupedPlan();
+    if (!pl) return QGEMM_ERR_ALLOC;
+    pl->ta = ta;
+    pl->tb = tb;
+    pl->s.conjA = ca ? 1 : 0;
+    pl->s.conjB = cb ? 1 : 0;
+    pl->nterms = nterms;
+    for (int i = 0; i < 4; ++i) {
+        pl->s.alpha[i] = alpha[i];
+        pl->s.beta[i] = beta[i];
+    }
+    std::vector<DevProblem> hp((size_t)count);
+    std::vector<int4> items;
+    std::vector<double> cost;
+    for (int64_t i = 0; i < count; ++i) {
+        const ::qgemm_problem_t &q = probs[i];
+        DevProblem &d = hp[(size_t)i];
+        d.A = static_cast<const float *>(q.A);
+        d.B = static_cast<const float *>(q.B);
+        d.C = static_cast<float *>(q.C);
+        d.lda = q.lda;
+        d.ldb = q.ldb;
+        d.ldc = q.ldc;
+        d.M = (int)q.M;
+        d.N = (int)q.N;
+        d.K = (int)q.K;
+        d.pad = 0;
+        if (q.M == 0 || q.N == 0) continue;
+        const int cls = force_class >= 0 ? force_class : grouped_tile_class(q.M, q.N, q.K);
+        const int tm = (int)((q.M + kBM[cls] - 1) / kBM[cls]);
+        const int tn = (int)((q.N + kBN[cls] - 1) / kBN[cls]);
+        const int64_t kp = ((q.K + kBK - 1) / kBK) * kBK;
+        for (int a = 0; a < tm; ++a)
+            for (int b = 0; b < tn; ++b) {
+                items.push_back(make_int4((int)i, a, b, cls));
+                // padded MFMA work of the tile plus a fixed cost of one tile start/epilogue
+                cost.push_back((double)kBM[cls] * kBN[cls] * (double)(kp + 48));
+            }
+        pl->class_count[cls] += (int64_t)tm * tn;
+    }
+    pl->nitems = (int64_t)items.size();
+    if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return QGEMM_ERR_HIP; }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
+        delete pl;
+        return QGEMM_ERR_HIP;
+    }
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(cus, pl->nitems));
+    pl->grid = (int)G;
+    // longest processing time first: each item to the least loaded block
+    std::vector<int64_t> order(items.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    using Slot = std::pair<double, int>;
+    std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+    for (int b = 0; b < G; ++b) heap.push({0.0, b});
+    std::vector<std::vector<int4>> per((size_t)G);
+    for (int64_t k : order) {
+        Slot s = heap.top();
+        heap.pop();
+        per[(size_t)s.second].push_back(items[(size_t)k]);
+        heap.push({s.first + cost[(size_t)k], s.second});
+    }
+    std::vector<int4> flat;
+    flat.reserve(items.size());
+    std::vector<int> starts((size_t)G + 1, 0);
+    for (int b = 0; b < G; ++b) {
+        starts[(size_t)b] = (int)flat.size();
+        flat.insert(flat.end(), per[(size_t)b].begin(), per[(size_t)b].end());
+    }
+    starts[(size_t)G] = (int)flat.size();
+
+    auto fail = [&](int code) {
+        (void)hipFree(pl->d_probs);
+        (void)hipFree(pl->d_items);
+        (void)hipFree(pl->d_starts);
+        delete pl;
+        return code;
+    };
+    if (hipMalloc(&pl->d_probs, sizeof(DevProblem) * std::max<size_t>(1, hp.size())) != hipSuccess)
+        return fail(QGEMM_ERR_ALLOC);
+    if (hipMalloc(&pl->d_items, sizeof(int4) * std::max<size_t>(1, flat.size())) != hipSuccess)
+        return fail(QGEMM_ERR_ALLOC);
+    if (hipMalloc(&pl->d_starts, sizeof(int) * starts.size()) != hipSuccess) return fail(QGEMM_ERR_ALLOC);
+    if (!hp.empty() &&
+        hipMemcpy(pl->d_probs, hp.data(), sizeof(DevProblem) * hp.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(QGEMM_ERR_HIP);
+    if (!flat.empty() &&
+        hipMemcpy(pl->d_items, flat.data(), sizeof(int4) * flat.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(QGEMM_ERR_HIP);
+    if (hipMemcpy(pl->d_starts, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(QGEMM_ERR_HIP);
+    *out = pl;
+    return QGEMM_OK;
+}
+
+int grouped_plan_run(const GroupedPlan *pl, hipStream_t stream)
+{
+    if (pl->nitems == 0) return QGEMM_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != pl->device) return QGEMM_ERR_INVALID_ARG;
+    const int panel_tiles = kSplitPanel / kBK;
+    hipError_t e;
+    const dim3 grid((unsigned)pl->grid);
+    switch (pl->nterms) {
+    case 3: e = launch_n<3>(pl->ta, pl->tb, grid, stream, pl->d_probs, pl->d_items, pl->d_starts, pl->s, panel_tiles); break;
+    case 9: e = launch_n<9>(pl->ta, pl->tb, grid, stream, pl->d_probs, pl->d_items, pl->d_starts, pl->s, panel_tiles); break;
+    default: e = launch_n<6>(pl->ta, pl->tb, grid, stream, pl->d_probs, pl->d_items, pl->d_starts, pl->s, panel_tiles); break;
+    }
+    return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
+}
+
+void grouped_plan_destroy(GroupedPlan *pl)
+{
+    if (!pl) return;
+    (void)hipFree(pl->d_probs);
+    (void)hipFree(pl->d_items);
+    (void)hipFree(pl->d_starts);
+    delete pl;
+}
+
+void grouped_plan_info(const GroupedPlan *pl, int64_t *nitems, int *grid, int64_t *class_count)
+{
+    if (nitems) *nitems = pl->nitems;
+    if (grid) *grid = pl->grid;
+    if (class_count)
+        for (int c = 0; c < kClasses; ++c) class_count[c] = pl->class_count[c];
+}
+
+}  // namespace qg

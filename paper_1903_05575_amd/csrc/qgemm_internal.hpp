@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/qgemm.h"
+
 namespace qg {
 
 // Quaternion-level description of one GEMM launch, already validated.
@@ -37,6 +39,16 @@ hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream);
 // (and the beta term) is written to that FP64 array instead of d.C.
 hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream);
 constexpr int kSplitPanel = 64;
+// Grouped (batched) split-BF16 plans; see qgemm_grouped.hip.
+struct GroupedPlan;
+constexpr int kGroupedClasses = 5;
+int grouped_tile_class(int64_t M, int64_t N, int64_t K);
+int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, int nterms, const double alpha[4],
+                        const double beta[4], int64_t count, const ::qgemm_problem_t *probs, int force_class);
+int grouped_plan_run(const GroupedPlan *pl, hipStream_t stream);
+void grouped_plan_destroy(GroupedPlan *pl);
+void grouped_plan_info(const GroupedPlan *pl, int64_t *nitems, int *grid, int64_t *class_count);
+
 // Y <- s X elementwise (left scalar), M x N quaternions.
 template <typename T>
 hipError_t launch_scale_left(const T *X, int64_t ldx, T *Y, int64_t ldy, int M, int N, const double s[4],

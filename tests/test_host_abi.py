@@ -1,0 +1,118 @@
+"""Host-only checks of the C ABI (no GPU needed): the library loads, exports
+every symbol of include/qgemm.h, and its argument validation rejects bad
+calls before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "qgemm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qgemm_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_1903_05575_amd as q
+    return q.lib()
+
+
+def test_exports_all_declared(L):
+    syms = header_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+    import paper_1903_05575_amd._lib as lb
+    assert set(lb.exported_symbols()) == set(syms)
+
+
+def q4(*v):
+    return (ctypes.c_double * 4)(*v)
+
+
+ONE = q4(1, 0, 0, 0)
+FAKE = 0x10000        # aligned, never dereferenced: validation fails first
+
+
+def call_d(L, opA=0, opB=0, M=4, N=4, K=4, alpha=ONE, A=FAKE, lda=4, B=FAKE, ldb=4, beta=ONE, C=FAKE, ldc=4):
+    return L.qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, None)
+
+
+@pytest.mark.parametrize("kw,arg,status", [
+    (dict(opA=7), 1, 1), (dict(opB=-1), 2, 1), (dict(M=-1), 3, 1), (dict(N=-2), 4, 1), (dict(K=-3), 5, 1),
+    (dict(M=1 << 31), 3, 5), (dict(alpha=None), 6, 1), (dict(lda=3), 8, 1), (dict(ldb=3), 10, 1),
+    (dict(beta=None), 11, 1), (dict(ldc=3), 13, 1), (dict(A=None), 7, 1), (dict(B=None), 9, 1),
+    (dict(C=None), 12, 1), (dict(A=FAKE + 8), 7, 2), (dict(B=FAKE + 16), 9, 2), (dict(C=FAKE + 24), 12, 2),
+])
+def test_validation_d(L, kw, arg, status):
+    rc = call_d(L, **kw)
+    assert rc == status
+    assert L.qgemm_last_invalid_arg() == arg
+
+
+def test_transposed_ld_rules(L):
+    # op T on A: stored K x M -> lda >= K
+    assert call_d(L, opA=1, M=8, K=5, lda=4) == 1 and L.qgemm_last_invalid_arg() == 8
+    # op C on B: stored N x K -> ldb >= N
+    assert call_d(L, opB=2, N=9, K=4, ldb=8) == 1 and L.qgemm_last_invalid_arg() == 10
+    # op T on A with lda = K is valid (N = 0: nothing is launched)
+    assert call_d(L, opA=1, M=8, K=4, lda=4, ldc=8, N=0) == 0
+    # K == 0 or alpha == 0: A and B may be NULL
+    assert call_d(L, K=0, A=None, B=None, N=0) == 0
+    assert call_d(L, alpha=q4(0, 0, 0, 0), A=None, B=None, N=0) == 0
+
+
+def test_validation_s_split_terms(L):
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, 4, ONE, FAKE, 4, 5, None)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 14
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE + 8, 4, FAKE, 4, ONE, FAKE, 4, 6, None)
+    assert rc == 2 and L.qgemm_last_invalid_arg() == 7
+
+
+def test_validation_backward(L):
+    rc = L.qgemm_backward_d(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, 4, FAKE, 3, ONE, FAKE, 4, FAKE, 4, FAKE, 4, None)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 12
+    rc = L.qgemm_backward_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, 4, FAKE, 4, ONE, FAKE, 4, FAKE, 4, FAKE, 4, 4, None)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 20
+    rc = L.qgemm_backward_d(0, 1, 4, 4, 4, ONE, FAKE, 4, FAKE, 4, FAKE, 4, ONE, FAKE, 4, FAKE, 3, None, 0, None)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 17
+
+
+def test_batched_plan_validation(L):
+    import paper_1903_05575_amd._lib as lb
+    probs = (lb.Problem * 3)()
+    for i in range(3):
+        probs[i] = lb.Problem(4, 4, 4, 4, 4, 4, FAKE, FAKE, FAKE)
+    probs[1].ldb = 2
+    h = ctypes.c_void_p()
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 10 and L.qgemm_last_invalid_problem() == 1
+    probs[1].ldb = 4
+    probs[2].C = FAKE + 4
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
+    assert rc == 2 and L.qgemm_last_invalid_arg() == 12 and L.qgemm_last_invalid_problem() == 2
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, 5)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 9
+    assert L.qgemm_batched_run(None, None) == 1
+    assert L.qgemm_batched_plan_destroy(None) == 0
+
+
+def test_status_strings(L):
+    for code, name in [(0, b"QGEMM_OK"), (1, b"QGEMM_ERR_INVALID_ARG"), (2, b"QGEMM_ERR_MISALIGNED"),
+                       (3, b"QGEMM_ERR_HIP"), (4, b"QGEMM_ERR_ALLOC"), (5, b"QGEMM_ERR_UNSUPPORTED")]:
+        assert L.qgemm_status_string(code) == name
+    assert L.qgemm_status_string(99) == b"QGEMM_ERR_UNKNOWN"
+
+
+def test_python_binding_checks_storage():
+    """The binding refuses tensors too small for the sizes passed (host check)."""
+    import torch
+    import paper_1903_05575_amd as q
+    from paper_1903_05575_amd import _lib
+    with pytest.raises(ValueError):
+        _lib._check_storage(torch.zeros(3, 4, 4), 4, 4, 4, torch.float32, "A")
