@@ -108,6 +108,133 @@ def cpu_baseline(p, ncols):
                       f"({q.flops(M, ncols, K):.3g} flops in {dt:.1f} s)"}
 
 
+def relfro(got, want):
+    den = np.linalg.norm(want)
+    return float(np.linalg.norm(np.asarray(got, np.float64) - want) / (den if den > 0 else 1.0))
+
+
+def variant_split(steps, warmup):
+    """FP32 4096^3 op N/C on the split-BF16 path (N(0,1) entries and the
+    row-scaled case) beside the FP64 path on the same widened data; error
+    against the oracle on a seeded 256 x 48 sample of C."""
+    import oracle
+    out = {}
+    n = 4096
+    fl = q.flops(n, n, n)
+    for scaled in (False, True):
+        p = W.gemm_precision(n, scaled=scaled)
+        A, B = dev(p["A"]), dev(p["B"])
+        C = torch.zeros((n, n, 4), dtype=torch.float32, device="cuda")
+        wall, ev = time_launches(lambda: q.qgemm_s("N", "C", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),
+                                 steps, warmup)
+        g = np.random.default_rng(11 + scaled)
+        rows = np.sort(g.choice(n, 256, replace=False))
+        cols = np.sort(g.choice(n, 48, replace=False))
+        want = oracle.qgemm_entries("N", "C", n, p["alpha"], p["A"], p["B"], p["beta"],
+                                    p["C"].astype(np.float64), rows, cols)
+        got = C.cpu().numpy()[cols][:, rows]
+        key = "split_bf16_4096_NC" + ("_rowscaled" if scaled else "")
+        tf = fl / (ev * 1e-3) / 1e12
+        out[key] = {"ms": round(ev, 3), "tflops_effective": round(tf, 2),
+                    "bf16_mfma_utilization": round(6 * tf / PEAK_BF16, 4), "split_terms": 6,
+                    "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}
+        if not scaled:
+            A64, B64 = A.double(), B.double()
+            C64 = torch.zeros((n, n, 4), dtype=torch.float64, device="cuda")
+            wall64, ev64 = time_launches(
+                lambda: q.qgemm_d("N", "C", n, n, n, p["alpha"], A64, n, B64, n, p["beta"], C64, n),
+                max(1, steps // 2), 1)
+            got64 = C64.cpu().numpy()[cols][:, rows]
+            out["fp64_4096_NC_same_data"] = {"ms": round(ev64, 3),
+                                              "tflops_effective": round(fl / (ev64 * 1e-3) / 1e12, 2),
+                                              "rel_err_vs_oracle_sampled": float(f"{relfro(got64, want):.3e}")}
+            out[key]["speedup_vs_fp64_path"] = round(ev64 / ev, 2)
+            del A64, B64, C64
+        del A, B, C
+        torch.cuda.empty_cache()
+    return out
+
+
+def variant_grouped(steps, warmup):
+    """4096 FP32 problems, M, N, K log-uniform in [8, 512], op N/N, alpha = 1,
+    beta = 0.5: one persistent launch replayed from a captured graph; error
+    on 64 sampled problems (the first replay's output, C restored before)."""
+    import oracle
+    w = W.grouped()
+    probs = [dict(pr, A=dev(pr["A"]), B=dev(pr["B"]), C=dev(pr["C"])) for pr in w["problems"]]
+    plan = q.GroupedPlan(probs, "N", "N", w["alpha"], w["beta"])
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        plan.run()
+    graph.replay()
+    torch.cuda.synchronize()
+    g = np.random.default_rng(3)
+    sample = sorted(g.choice(len(probs), 64, replace=False))
+    err = 0.0
+    for i in sample:
+        pr = w["problems"][i]
+        want = oracle.qgemm("N", "N", pr["M"], pr["N"], pr["K"], w["alpha"], pr["A"], pr["lda"], pr["B"],
+                            pr["ldb"], w["beta"], pr["C"], pr["ldc"])
+        err = max(err, relfro(probs[i]["C"].cpu().numpy(), want))
+    wall, ev = time_launches(graph.replay, steps * 4, warmup)
+    fl = sum(q.flops(pr["M"], pr["N"], pr["K"]) for pr in w["problems"])
+    by = sum(16 * (pr["M"] * pr["K"] + pr["K"] * pr["N"] + 2 * pr["M"] * pr["N"]) for pr in w["problems"])
+    tf = fl / (ev * 1e-3) / 1e12
+    info = plan.info()
+    plan.close()
+    return {"grouped_4096_fp32": {"ms": round(ev, 3), "tflops_effective": round(tf, 2),
+                                  "bf16_mfma_utilization": round(6 * tf / PEAK_BF16, 4),
+                                  "algorithmic_gbps": round(by / (ev * 1e-3) / 1e9, 1),
+                                  "hbm_frac": round(by / (ev * 1e-3) / 1e9 / PEAK_HBM, 4),
+                                  "graph_replay": True, "work_items": info["work_items"],
+                                  "worst_rel_err_64_sampled_problems": float(f"{err:.3e}")}}
+
+
+def variant_linear(steps, warmup):
+    """Quaternion linear layer Y = X W, X 8192 x 1024, W 1024 x 1024 (FP32,
+    Glorot), forward + hand-written backward (dX, dW) through torch.autograd;
+    error on sampled rows of Y and dX against the oracle."""
+    import oracle
+    p = W.linear_layer()
+    M, K, N = p["M"], p["K"], p["N"]
+    X = dev(p["X"]).requires_grad_(True)
+    layer = q.QLinear(K, N)
+    with torch.no_grad():
+        layer.weight.copy_(dev(p["W"]))
+    dY = dev(p["dY"])
+
+    def fwd():
+        return layer(X)
+
+    def fwd_bwd():
+        X.grad = None
+        layer.weight.grad = None
+        layer(X).backward(dY)
+
+    _, ev_f = time_launches(fwd, steps, warmup)
+    _, ev_fb = time_launches(fwd_bwd, steps, warmup)
+    Y = fwd().detach().cpu().numpy()
+    fwd_bwd()
+    dX = X.grad.cpu().numpy()
+    g = np.random.default_rng(5)
+    rows = np.sort(g.choice(M, 32, replace=False))
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    Xs = p["X"][:, rows, :].astype(np.float64)
+    Wd = p["W"].astype(np.float64)
+    Ys = oracle.qgemm("N", "N", 32, N, K, one, Xs, 32, Wd, K, zero, np.zeros((N, 32, 4)), 32)
+    dXs, _, _ = oracle.qgemm_backward("N", "N", 32, N, K, one, Xs, 32, Wd, K,
+                                      p["dY"][:, rows, :].astype(np.float64), 32, zero,
+                                      want_dB=False, want_dC0=False)
+    fl = 3 * q.flops(M, N, K)
+    return {"linear_8192x1024x1024_fp32": {
+        "forward_ms": round(ev_f, 3), "forward_backward_ms": round(ev_fb, 3),
+        "tflops_effective_fwd_bwd": round(fl / (ev_fb * 1e-3) / 1e12, 2),
+        "rel_err_Y_sampled": float(f"{relfro(Y[:, rows], Ys):.3e}"),
+        "rel_err_dX_sampled": float(f"{relfro(dX[:, rows], dXs):.3e}")}}
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -181,14 +308,21 @@ def main():
     }
     del A, B, C
     torch.cuda.empty_cache()
+    if not args.no_variants:
+        variants = {}
+        for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear)):
+            log(f"[bench] variant {name}")
+            variants.update(fn(args.steps, args.warmup))
+            torch.cuda.empty_cache()
+        line["variants"] = variants
     if not args.no_cpu_baseline:
         import oracle
-        # size the column sample for about 15 s of oracle time on this host
+        # size the column sample for about 20 s of oracle time on this host
         probe_cols = max(8, oracle.max_threads())
         t0 = time.perf_counter()
         cpu_baseline(p, probe_cols)
         per_col = (time.perf_counter() - t0) / probe_cols
-        ncols = int(min(n, max(probe_cols, 15.0 / max(per_col, 1e-6))))
+        ncols = int(min(n, max(probe_cols, 20.0 / max(per_col, 1e-6))))
         ncols -= ncols % probe_cols if ncols > probe_cols else 0
         log(f"[bench] CPU oracle baseline on {ncols} columns")
         line["cpu_baseline"] = cpu_baseline(p, ncols)
