@@ -154,6 +154,12 @@ qgemm_status_t backward_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, 
     if (misaligned(dA)) return fail(QGEMM_ERR_MISALIGNED, 14);
     if (misaligned(dB)) return fail(QGEMM_ERR_MISALIGNED, 16);
     if (misaligned(dC0)) return fail(QGEMM_ERR_MISALIGNED, 18);
+    if constexpr (sizeof(T) == 4) {
+        // the two gradient GEMMs read (G, op(B)^H) and (op(A)^H, G) through the split tile
+        if (!qg::split_ld_supported(ldg, ldb, false, !op_transposes(opB)) ||
+            !qg::split_ld_supported(lda, ldg, !op_transposes(opA), false))
+            return fail(QGEMM_ERR_UNSUPPORTED, 8);
+    }
     if ((need_a && (dA == (const T *)A || dA == (const T *)B || dA == (const T *)G)) ||
         (need_b && (dB == (const T *)A || dB == (const T *)B || dB == (const T *)G)))
         return fail(QGEMM_ERR_INVALID_ARG, need_a ? 14 : 16);
@@ -229,6 +235,8 @@ static qgemm_status_t split_common(int opA, int opB, int64_t M, int64_t N, int64
     if (split_terms == 0) split_terms = 6;
     if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 14);
     if (M == 0 || N == 0) return QGEMM_OK;
+    if (!qg::split_ld_supported(lda, ldb, op_transposes(opA), op_transposes(opB)))
+        return fail(QGEMM_ERR_UNSUPPORTED, op_transposes(opA) ? 8 : 10);
     auto d = make_desc<float>(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     if (qg::launch_qgemm_bf16x3(d, C64, split_terms, qg::kSplitPanel, static_cast<hipStream_t>(stream)) != hipSuccess)
         return QGEMM_ERR_HIP;
@@ -301,6 +309,10 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
     qg::GroupedPlan *impl = nullptr;
     int rc = qg::grouped_plan_create(&impl, op_transposes(opA), op_transposes(opB), op_conjugates(opA),
                                      op_conjugates(opB), split_terms, alpha, beta, count, problems, tile_class);
+    if (rc < 0) {
+        g_bad_problem = -(int64_t)rc - 1;
+        return fail(QGEMM_ERR_UNSUPPORTED, 5);
+    }
     if (rc != QGEMM_OK) return (qgemm_status_t)rc;
     qgemm_plan_s *h = new (std::nothrow) qgemm_plan_s{impl};
     if (!h) {

@@ -1,7 +1,8 @@
 // Single FP32-stored quaternion GEMM on the split-BF16 tile of
 // qgemm_bf16x3_tile.hpp: one 64 x 64-quaternion tile per block, four waves
 // stacked along M (each 16 rows x 64 columns = 2 x 2 MFMA blocks), K-tiles of
-// 16 quaternions, blocks ordered XCD-aware.
+// 16 quaternions through one LDS stage, two blocks per CU, blocks ordered
+// XCD-aware.
 #include "qgemm_bf16x3_tile.hpp"
 
 namespace qg {
@@ -9,24 +10,29 @@ namespace {
 
 using TL = split::Tile<64, 64, 4, 1, 16>;
 
-template <bool TA, bool TB, int NTERMS, bool C64>
-__global__ __launch_bounds__(split::NT, 1) void qgemm_bf16x3_kernel(GemmDesc<float> p, double *c64, int tiles_m,
-                                                                  int tiles_n, int nk, int panel_tiles)
+template <bool TA, bool TB, int NTERMS, bool C64, int STAGES>
+__global__ __launch_bounds__(split::NT, STAGES == 1 ? 2 : 1) void qgemm_bf16x3_kernel(GemmDesc<float> p, double *c64,
+                                                                                   int tiles_m, int tiles_n, int nk,
+                                                                                   int panel_tiles)
 {
     extern __shared__ unsigned lds[];
     int tm, tn;
     xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
-    split::split_tile<TL, TA, TB, NTERMS, C64>(p, c64, tm * TL::BM, tn * TL::BN, nk, panel_tiles, lds);
+    if (p.has_bscale)
+        split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, true>(p, c64, tm * TL::BM, tn * TL::BN, nk, panel_tiles, lds);
+    else
+        split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, false>(p, c64, tm * TL::BM, tn * TL::BN, nk, panel_tiles, lds);
 }
 
-template <bool TA, bool TB, int NTERMS, bool C64>
-hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
+template <bool TA, bool TB, int NTERMS, bool C64, int STAGES>
+hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
 {
-    auto kern = &qgemm_bf16x3_kernel<TA, TB, NTERMS, C64>;
+    auto kern = &qgemm_bf16x3_kernel<TA, TB, NTERMS, C64, STAGES>;
+    constexpr size_t lds_bytes = STAGES == 1 ? TL::LDS_BYTES_1 : TL::LDS_BYTES;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)TL::LDS_BYTES);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -38,9 +44,17 @@ hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_
     const int64_t nblocks = (int64_t)tiles_m * tiles_n;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(split::NT), TL::LDS_BYTES, stream, d, c64, tiles_m,
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(split::NT), lds_bytes, stream, d, c64, tiles_m,
                        tiles_n, nk, panel_tiles);
     return hipGetLastError();
+}
+
+// One LDS stage and two resident blocks per CU: measured faster than two
+// stages with one block (the second block's MFMAs cover this block's staging).
+template <bool TA, bool TB, int NTERMS, bool C64>
+hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
+{
+    return launch_s<TA, TB, NTERMS, C64, 1>(d, c64, panel, stream);
 }
 
 template <int NTERMS, bool C64>
@@ -56,6 +70,7 @@ hipError_t dispatch_ops(const GemmDesc<float> &d, double *c64, int panel, hipStr
 
 hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream)
 {
+    if (!split::split_offsets_fit(d.lda, d.ldb, d.opA_t, d.opB_t, TL::BM, TL::BN, TL::BK)) return hipErrorInvalidValue;
     if (c64) {
         switch (nterms) {
         case 3: return dispatch_ops<3, true>(d, c64, panel, stream);

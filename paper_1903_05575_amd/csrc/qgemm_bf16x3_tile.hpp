@@ -34,8 +34,7 @@
 //
 // Tile.  A block of 256 threads (4 waves, arranged WR x WC) computes BM x BN
 // quaternions; a wave owns (BM/WR) x (BN/WC) = MB x NB MFMA blocks.  K
-// advances in tiles of BK quaternions through two LDS stages (the next tile is
-// fetched into registers while the current one is multiplied).
+// advances in tiles of BK quaternions through one or two LDS stages.
 // LDS (32-bit words): per stage, A as [piece][row][kappa][2 words] and B as
 // [piece][column][kappa][2 words], row pitch 2 BK + 4 words.  The 16-byte pad
 // spreads the 16-byte fragment reads of consecutive rows over the banks.
@@ -136,7 +135,8 @@ struct Tile {
     static constexpr int A_STAGE = 3 * BM * RP;
     static constexpr int B_STAGE = 3 * BN * RP;
     static constexpr int STAGE = A_STAGE + B_STAGE;
-    static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(unsigned);
+    static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(unsigned);   // two stages
+    static constexpr size_t LDS_BYTES_1 = STAGE * sizeof(unsigned);     // one stage
     static constexpr int A_Q = BM * BK / NT;                   // quaternions of A per thread per K-tile
     static constexpr int B_Q = BN * BK / NT;
     static_assert(WR * WC == 4, "four waves per block");
@@ -147,8 +147,18 @@ struct Tile {
 
 // Compute the BM x BN output tile at (m0, n0) of problem p and write it.
 // nk = number of K-tiles to walk (0 when alpha == 0).  `lds` must hold
-// Tile::LDS_BYTES.  Every thread of the block must call this.
-template <class TL, bool TA, bool TB, int NTERMS, bool C64>
+// TL::LDS_BYTES (STAGES = 2) or TL::LDS_BYTES_1 (STAGES = 1).  Every thread of
+// the block must call this.  With STAGES = 2 the next K-tile is fetched into
+// registers while the current one is multiplied; with STAGES = 1 the block
+// stages, synchronises and multiplies in turn and relies on a second resident
+// block per CU to keep the matrix cores busy meanwhile.  BS: op(B) is scaled by
+// p.bscale from the left at staging.
+// Loads are buffer loads from a per-K-tile resource: a masked element gets
+// the offset kOob, which the hardware reads as zero, so the K-loop has no
+// branches.  In-tile byte offsets are below 2^31 (see split_offsets_fit).
+constexpr unsigned kOob = 0x80000000u;
+
+template <class TL, bool TA, bool TB, int NTERMS, bool C64, int STAGES, bool BS = false>
 __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64, int m0, int n0, int nk,
                                            int panel_tiles, unsigned *lds)
 {
@@ -161,7 +171,14 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
 
     const int fi = lane & 31;                 // A row / B column within the 32-wide MFMA block
     const int fg = lane >> 5;                 // k group: quaternions 2fg, 2fg+1 of the step
-    const LRow L = lrow(fi & 3);
+    LRow L = lrow(fi & 3);
+    if (p.conjA) {
+        // conj(a) negates a1..a3: flip the halves of each output word that come from them
+        const int r = fi & 3;
+        L.neg0 ^= r == 0 ? 0x80000000u : r == 1 ? 0x00008000u : 0x80008000u;
+        L.neg1 ^= r == 1 ? 0x80008000u : r == 2 ? 0x80000000u : r == 3 ? 0x00008000u : 0x80008000u;
+    }
+    const unsigned conjB = p.conjB ? 0x80000000u : 0u;
     const int a_row = wr * (BM / TL::WR) + (fi >> 2);   // + 8 m
     const int b_row = wc * (BN / TL::WC) + fi;          // + 32 n
 
@@ -174,87 +191,77 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
             tot[m][n] = (f32x16){};
         }
 
-    f32x4 ra[TL::A_Q], rb[TL::B_Q];
-
-    auto a_coords = [&](int i, int &row, int &ka) {
+    // per-slot coordinates, in-tile byte offsets (kOob where the row is outside the matrix)
+    int a_r[TL::A_Q], a_k[TL::A_Q], b_c[TL::B_Q], b_k[TL::B_Q];
+    unsigned a_off[TL::A_Q], b_off[TL::B_Q];
+#pragma unroll
+    for (int i = 0; i < TL::A_Q; ++i) {
         const int qd = tid + NT * i;
-        if (!TA) { row = qd % BM; ka = qd / BM; }     // stored contiguous along mu
-        else     { ka = qd % BK; row = qd / BK; }     // stored contiguous along kappa
-    };
-    auto b_coords = [&](int i, int &col, int &ka) {
+        if (!TA) { a_r[i] = qd % BM; a_k[i] = qd / BM; }     // stored contiguous along mu
+        else     { a_k[i] = qd % BK; a_r[i] = qd / BK; }     // stored contiguous along kappa
+        a_off[i] = m0 + a_r[i] < p.M ? 16u * (TA ? (unsigned)a_r[i] * (unsigned)p.lda + a_k[i]
+                                                 : (unsigned)a_k[i] * (unsigned)p.lda + a_r[i])
+                                     : kOob;
+    }
+#pragma unroll
+    for (int i = 0; i < TL::B_Q; ++i) {
         const int qd = tid + NT * i;
-        if (!TB) { ka = qd % BK; col = qd / BK; }
-        else     { col = qd % BN; ka = qd / BN; }
-    };
+        if (!TB) { b_k[i] = qd % BK; b_c[i] = qd / BK; }
+        else     { b_c[i] = qd % BN; b_k[i] = qd / BN; }
+        b_off[i] = n0 + b_c[i] < p.N ? 16u * (TB ? (unsigned)b_k[i] * (unsigned)p.ldb + b_c[i]
+                                                 : (unsigned)b_c[i] * (unsigned)p.ldb + b_k[i])
+                                     : kOob;
+    }
 
+    u32x4 ra[TL::A_Q], rb[TL::B_Q];
+
+    // fetch K-tile kt into registers (tiles at or past K read as zeros)
     auto load_tile = [&](int kt) {
         const int k0 = kt * BK;
+        const int krem = p.K - k0;
+        const float *Ab = p.A + 4 * (TA ? ((int64_t)m0 * p.lda + k0) : ((int64_t)k0 * p.lda + m0));
+        const float *Bb = p.B + 4 * (TB ? ((int64_t)k0 * p.ldb + n0) : ((int64_t)n0 * p.ldb + k0));
+        const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, 0x7fffffff, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, 0x7fffffff, 0x00020000);
 #pragma unroll
-        for (int i = 0; i < TL::A_Q; ++i) {
-            int row, ka;
-            a_coords(i, row, ka);
-            const int gm = m0 + row, gk = k0 + ka;
-            if (gm < p.M && gk < p.K) {
-                const int64_t e = TA ? ((int64_t)gm * p.lda + gk) : ((int64_t)gk * p.lda + gm);
-                ra[i] = *reinterpret_cast<const f32x4 *>(p.A + 4 * e);
-            } else {
-                ra[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            }
-        }
+        for (int i = 0; i < TL::A_Q; ++i)
+            ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA, a_k[i] < krem ? a_off[i] : kOob, 0, 0);
 #pragma unroll
-        for (int i = 0; i < TL::B_Q; ++i) {
-            int col, ka;
-            b_coords(i, col, ka);
-            const int gn = n0 + col, gk = k0 + ka;
-            if (gn < p.N && gk < p.K) {
-                const int64_t e = TB ? ((int64_t)gk * p.ldb + gn) : ((int64_t)gn * p.ldb + gk);
-                rb[i] = *reinterpret_cast<const f32x4 *>(p.B + 4 * e);
-            } else {
-                rb[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            }
-        }
+        for (int i = 0; i < TL::B_Q; ++i)
+            rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rB, b_k[i] < krem ? b_off[i] : kOob, 0, 0);
     };
 
-    auto put = [&](unsigned *plane0, int plane_words, int row, int ka, f32x4 v) {
+    auto put = [&](unsigned *plane0, int plane_words, int row, int ka, float x, float y, float z, float w) {
         unsigned h0, md0, l0, h1, md1, l1;
-        split2(v.x, v.y, h0, md0, l0);
-        split2(v.z, v.w, h1, md1, l1);
+        split2(x, y, h0, md0, l0);
+        split2(z, w, h1, md1, l1);
         unsigned *d = plane0 + row * RP + 2 * ka;
         *reinterpret_cast<uint2 *>(d) = make_uint2(h0, h1);
         *reinterpret_cast<uint2 *>(d + plane_words) = make_uint2(md0, md1);
         *reinterpret_cast<uint2 *>(d + 2 * plane_words) = make_uint2(l0, l1);
     };
 
-    auto store_tile = [&](int stage) {
-        unsigned *As = lds + stage * TL::STAGE;
+    auto store_tile = [&](unsigned *As) {
         unsigned *Bs = As + TL::A_STAGE;
 #pragma unroll
-        for (int i = 0; i < TL::A_Q; ++i) {
-            int row, ka;
-            a_coords(i, row, ka);
-            f32x4 v = ra[i];
-            if (p.conjA) { v.y = -v.y; v.z = -v.z; v.w = -v.w; }
-            put(As, BM * RP, row, ka, v);
-        }
+        for (int i = 0; i < TL::A_Q; ++i)   // conj(A) is applied through L
+            put(As, BM * RP, a_r[i], a_k[i], __uint_as_float(ra[i].x), __uint_as_float(ra[i].y),
+                __uint_as_float(ra[i].z), __uint_as_float(ra[i].w));
 #pragma unroll
         for (int i = 0; i < TL::B_Q; ++i) {
-            int col, ka;
-            b_coords(i, col, ka);
-            f32x4 v = rb[i];
-            if (p.conjB) { v.y = -v.y; v.z = -v.z; v.w = -v.w; }
-            if (p.has_bscale) {
-                const float s[4] = {(float)p.bscale[0], (float)p.bscale[1], (float)p.bscale[2], (float)p.bscale[3]};
-                const float b[4] = {v.x, v.y, v.z, v.w};
+            float b[4] = {__uint_as_float(rb[i].x), __uint_as_float(rb[i].y ^ conjB),
+                          __uint_as_float(rb[i].z ^ conjB), __uint_as_float(rb[i].w ^ conjB)};
+            if constexpr (BS) {
+                const float sc[4] = {(float)p.bscale[0], (float)p.bscale[1], (float)p.bscale[2], (float)p.bscale[3]};
                 float t[4];
-                qmul(s, b, t);
-                v = (f32x4){t[0], t[1], t[2], t[3]};
+                qmul(sc, b, t);
+                b[0] = t[0]; b[1] = t[1]; b[2] = t[2]; b[3] = t[3];
             }
-            put(Bs, BN * RP, col, ka, v);
+            put(Bs, BN * RP, b_c[i], b_k[i], b[0], b[1], b[2], b[3]);
         }
     };
 
-    auto compute = [&](int stage) {
-        const unsigned *As = lds + stage * TL::STAGE;
+    auto compute = [&](const unsigned *As) {
         const unsigned *Bs = As + TL::A_STAGE;
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
@@ -294,18 +301,41 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
             }
     };
 
-    if (nk > 0) {
-        load_tile(0);
-        store_tile(0);
-        __syncthreads();
-    }
-    for (int kt = 0; kt < nk; ++kt) {
-        const int stage = kt & 1;
-        if (kt + 1 < nk) load_tile(kt + 1);
-        compute(stage);
-        if ((kt + 1) % panel_tiles == 0) flush();
-        if (kt + 1 < nk) store_tile(stage ^ 1);
-        __syncthreads();
+    unsigned *S0 = lds;
+    if constexpr (STAGES == 2) {
+        unsigned *S1 = lds + TL::STAGE;
+        if (nk > 0) {
+            load_tile(0);
+            store_tile(S0);
+            __syncthreads();
+        }
+        // unrolled by two so that both stages are compile-time constants
+        int kt = 0;
+        while (kt < nk) {
+            load_tile(kt + 1);
+            compute(S0);
+            store_tile(S1);
+            __syncthreads();
+            ++kt;
+            if (kt % panel_tiles == 0) flush();
+            if (kt >= nk) break;
+            load_tile(kt + 1);
+            compute(S1);
+            store_tile(S0);
+            __syncthreads();
+            ++kt;
+            if (kt % panel_tiles == 0) flush();
+        }
+    } else {
+        for (int kt = 0; kt < nk; ++kt) {
+            load_tile(kt);
+            if (kt > 0) __syncthreads();                 // every wave is done reading the stage
+            store_tile(S0);
+            __syncthreads();
+            compute(S0);
+            if ((kt + 1) % panel_tiles == 0) flush();
+        }
+        __syncthreads();                                 // LDS may be reused by the caller
     }
     flush();
 
@@ -354,6 +384,17 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                     *dst = (f32x4){o[0], o[1], o[2], o[3]};
                 }
             }
+}
+
+// In-tile byte offsets of the largest tile must stay below 2^31 (the masked
+// offset kOob): the farthest element read is ((BM-1) lda + BK) for a
+// transposed A and (BK lda + BM) otherwise (likewise for B), 16 bytes each.
+inline bool split_offsets_fit(int64_t lda, int64_t ldb, bool ta, bool tb, int BM, int BN, int BK)
+{
+    const int64_t lim = (int64_t)1 << 31;
+    const int64_t fa = 16 * (ta ? (BM * lda + BK) : (BK * lda + BM));
+    const int64_t fb = 16 * (tb ? (BK * ldb + BN) : (BN * ldb + BK));
+    return fa < lim && fb < lim;
 }
 
 }  // namespace split

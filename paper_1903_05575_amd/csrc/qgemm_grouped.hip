@@ -8,7 +8,7 @@
 // blocks longest-processing-time first, each block receiving a contiguous
 // run of the item array.  Problem descriptors, items and per-block offsets
 // go to device memory once.
-// Run (capture-safe): a single launch of one block per CU; block b walks
+// Run (capture-safe): a single launch of two blocks per CU; block b walks
 // items [start[b], start[b+1]).  No allocation, copy, memset or atomic.
 #include "qgemm_bf16x3_tile.hpp"
 
@@ -43,9 +43,11 @@ constexpr int kClasses = 5;
 constexpr int kBM[kClasses] = {64, 32, 64, 32, 16};
 constexpr int kBN[kClasses] = {64, 64, 32, 32, 64};
 constexpr int kBK = 16;
-constexpr size_t kLds = T0::LDS_BYTES;   // the largest of the classes
-static_assert(T1::LDS_BYTES <= kLds && T2::LDS_BYTES <= kLds && T3::LDS_BYTES <= kLds && T4::LDS_BYTES <= kLds,
+constexpr size_t kLds = T0::LDS_BYTES_1;   // one stage of the largest class
+static_assert(T1::LDS_BYTES_1 <= kLds && T2::LDS_BYTES_1 <= kLds && T3::LDS_BYTES_1 <= kLds &&
+                  T4::LDS_BYTES_1 <= kLds,
               "LDS sized for the largest tile");
+constexpr int kBlocksPerCU = 2;
 
 struct Scalars {
     double alpha[4];
@@ -54,7 +56,7 @@ struct Scalars {
 };
 
 template <bool TA, bool TB, int NTERMS>
-__global__ __launch_bounds__(split::NT, 1) void grouped_kernel(const DevProblem *__restrict__ probs,
+__global__ __launch_bounds__(split::NT, kBlocksPerCU) void grouped_kernel(const DevProblem *__restrict__ probs,
                                                              const int4 *__restrict__ items,
                                                              const int *__restrict__ starts, Scalars s,
                                                              int panel_tiles)
@@ -90,11 +92,11 @@ __global__ __launch_bounds__(split::NT, 1) void grouped_kernel(const DevProblem 
         }
         const int nk = alpha_zero ? 0 : (pr.K + kBK - 1) / kBK;
         switch (it.w) {
-        case 0: split::split_tile<T0, TA, TB, NTERMS, false>(d, nullptr, it.y * 64, it.z * 64, nk, panel_tiles, lds); break;
-        case 1: split::split_tile<T1, TA, TB, NTERMS, false>(d, nullptr, it.y * 32, it.z * 64, nk, panel_tiles, lds); break;
-        case 2: split::split_tile<T2, TA, TB, NTERMS, false>(d, nullptr, it.y * 64, it.z * 32, nk, panel_tiles, lds); break;
-        case 3: split::split_tile<T3, TA, TB, NTERMS, false>(d, nullptr, it.y * 32, it.z * 32, nk, panel_tiles, lds); break;
-        default: split::split_tile<T4, TA, TB, NTERMS, false>(d, nullptr, it.y * 16, it.z * 64, nk, panel_tiles, lds); break;
+        case 0: split::split_tile<T0, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 64, it.z * 64, nk, panel_tiles, lds); break;
+        case 1: split::split_tile<T1, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 32, it.z * 64, nk, panel_tiles, lds); break;
+        case 2: split::split_tile<T2, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 64, it.z * 32, nk, panel_tiles, lds); break;
+        case 3: split::split_tile<T3, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 32, it.z * 32, nk, panel_tiles, lds); break;
+        default: split::split_tile<T4, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 16, it.z * 64, nk, panel_tiles, lds); break;
         }
         __syncthreads();                                 // LDS is reused by the next item
     }
@@ -186,6 +188,10 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         d.pad = 0;
         if (q.M == 0 || q.N == 0) continue;
         const int cls = force_class >= 0 ? force_class : grouped_tile_class(q.M, q.N, q.K);
+        if (!split::split_offsets_fit(q.lda, q.ldb, ta, tb, kBM[cls], kBN[cls], kBK)) {
+            delete pl;
+            return -(int)(i + 1);                  // caller reports QGEMM_ERR_UNSUPPORTED for problem i
+        }
         const int tm = (int)((q.M + kBM[cls] - 1) / kBM[cls]);
         const int tn = (int)((q.N + kBN[cls] - 1) / kBN[cls]);
         const int64_t kp = ((q.K + kBK - 1) / kBK) * kBK;
@@ -204,7 +210,7 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         delete pl;
         return QGEMM_ERR_HIP;
     }
-    const int64_t G = std::max<int64_t>(1, std::min<int64_t>(cus, pl->nitems));
+    const int64_t G = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * kBlocksPerCU, pl->nitems));
     pl->grid = (int)G;
     // longest processing time first: each item to the least loaded block
     std::vector<int64_t> order(items.size());

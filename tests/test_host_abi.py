@@ -116,3 +116,13 @@ def test_python_binding_checks_storage():
     from paper_1903_05575_amd import _lib
     with pytest.raises(ValueError):
         _lib._check_storage(torch.zeros(3, 4, 4), 4, 4, 4, torch.float32, "A")
+
+
+def test_split_unsupported_leading_dimension(L):
+    """The split-BF16 tiles address a K-tile with 32-bit offsets: a transposed
+    operand with lda >= 2^21 quaternions is refused as unsupported (host check)."""
+    big = 1 << 21
+    rc = L.qgemm_s(1, 0, 4, 4, 4, ONE, FAKE, big, FAKE, 4, ONE, FAKE, 4, 6, None)
+    assert rc == 5 and L.qgemm_last_invalid_arg() == 8
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, big * 4, ONE, FAKE, 4, 6, None)
+    assert rc == 5 and L.qgemm_last_invalid_arg() == 10
