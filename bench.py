@@ -17,6 +17,7 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    its error against the oracle on sampled outputs.
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
+    python bench.py --only fp64|split|grouped|linear    one part, no CPU baseline
 """
 import argparse
 import hashlib
@@ -255,6 +256,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear"],
+                    help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this library has no "
@@ -266,6 +269,11 @@ def main():
     q.lib()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+
+    if args.only in ("split", "grouped", "linear"):
+        fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear}[args.only]
+        print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
     n = args.size
@@ -308,6 +316,9 @@ def main():
     }
     del A, B, C
     torch.cuda.empty_cache()
+    if args.only == "fp64":
+        print(json.dumps(line), flush=True)
+        return
     if not args.no_variants:
         variants = {}
         for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear)):
