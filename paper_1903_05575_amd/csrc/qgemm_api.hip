@@ -154,10 +154,12 @@ qgemm_status_t backward_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, 
     if (misaligned(dA)) return fail(QGEMM_ERR_MISALIGNED, 14);
     if (misaligned(dB)) return fail(QGEMM_ERR_MISALIGNED, 16);
     if (misaligned(dC0)) return fail(QGEMM_ERR_MISALIGNED, 18);
-    if constexpr (sizeof(T) == 4) {
-        // the two gradient GEMMs read (G, op(B)^H) and (op(A)^H, G) through the split tile
-        if (!qg::split_ld_supported(ldg, ldb, false, !op_transposes(opB)) ||
-            !qg::split_ld_supported(lda, ldg, !op_transposes(opA), false))
+    {
+        // the two gradient GEMMs read (G, op(B)^H) and (op(A)^H, G) through the GEMM tiles
+        auto ok = [](int64_t l1, int64_t l2, bool t1, bool t2) {
+            return sizeof(T) == 4 ? qg::split_ld_supported(l1, l2, t1, t2) : qg::f64_ld_supported(l1, l2, t1, t2);
+        };
+        if (!ok(ldg, ldb, false, !op_transposes(opB)) || !ok(lda, ldg, !op_transposes(opA), false))
             return fail(QGEMM_ERR_UNSUPPORTED, 8);
     }
     if ((need_a && (dA == (const T *)A || dA == (const T *)B || dA == (const T *)G)) ||
@@ -220,6 +222,8 @@ qgemm_status_t qgemm_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const 
 {
     qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 32);
     if (s != QGEMM_OK || M == 0 || N == 0) return s;
+    if (!qg::f64_ld_supported(lda, ldb, op_transposes(opA), op_transposes(opB)))
+        return fail(QGEMM_ERR_UNSUPPORTED, op_transposes(opA) ? 8 : 10);
     const auto d = make_desc<double>(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     if (qg::launch_qgemm_f64(d, static_cast<hipStream_t>(stream)) != hipSuccess) return QGEMM_ERR_HIP;
     return QGEMM_OK;

@@ -148,10 +148,10 @@ struct Tile {
 // Compute the BM x BN output tile at (m0, n0) of problem p and write it.
 // nk = number of K-tiles to walk (0 when alpha == 0).  `lds` must hold
 // TL::LDS_BYTES (STAGES = 2) or TL::LDS_BYTES_1 (STAGES = 1).  Every thread of
-// the block must call this.  With STAGES = 2 the next K-tile is fetched into
+// the block must call this.  In both variants the next K-tile is fetched into
 // registers while the current one is multiplied; with STAGES = 1 the block
-// stages, synchronises and multiplies in turn and relies on a second resident
-// block per CU to keep the matrix cores busy meanwhile.  BS: op(B) is scaled by
+// then stages it into the single LDS stage between two barriers and relies on
+// a second resident block per CU to keep the matrix cores busy meanwhile.  BS: op(B) is scaled by
 // p.bscale from the left at staging.
 // Loads are buffer loads from a per-K-tile resource: a masked element gets
 // the offset kOob, which the hardware reads as zero, so the K-loop has no
@@ -327,11 +327,14 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
             if (kt % panel_tiles == 0) flush();
         }
     } else {
+        // one stage: the next K-tile's loads are issued before this tile's
+        // MFMAs so their latency hides behind the compute
+        if (nk > 0) load_tile(0);
         for (int kt = 0; kt < nk; ++kt) {
-            load_tile(kt);
             if (kt > 0) __syncthreads();                 // every wave is done reading the stage
             store_tile(S0);
             __syncthreads();
+            load_tile(kt + 1);
             compute(S0);
             if ((kt + 1) % panel_tiles == 0) flush();
         }

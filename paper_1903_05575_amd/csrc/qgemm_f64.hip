@@ -23,9 +23,14 @@
 //   wave w owns quaternion rows [16w, 16w+16) x all 64 columns = 4 x 4 MFMA
 //   blocks, 16 accumulators of 4 doubles.  Per kappa a wave reads 4 A and 4 B
 //   fragments (one 8-byte LDS read per lane each) and issues 16 MFMAs.
+//   Two blocks per CU (224 VGPRs), 16.6 + 16.6 KB of LDS per stage.
 //   K is walked in tiles of BK = 8 quaternions through two LDS stages: the
-//   next tile is fetched from HBM into registers while the current one is
-//   multiplied, then written to the other stage (one barrier per tile).
+//   next tile is fetched from HBM into registers at the start of a tile and
+//   written to the other stage in the middle of the current tile's MFMA
+//   stream (one barrier per tile).  Fragments of the next kappa step are read
+//   from LDS while the current step's 16 MFMAs run.  Operands are read with
+//   buffer loads; masked elements use an out-of-range offset that reads as
+//   zero, so the K-loop has no branches.
 // LDS layouts (doubles):
 //   A stage: [kappa][mu][4] with a row pitch of 4*BM + 4 (the pad spreads the
 //            transposed-operand writes over the banks); fragment reads of one
@@ -60,7 +65,9 @@ __device__ __forceinline__ double flip(double v, unsigned long long sign)
     return __longlong_as_double(__double_as_longlong(v) ^ (long long)sign);
 }
 
-template <bool TA, bool TB>
+constexpr unsigned kOob = 0x80000000u;   // buffer offset read as zero (masked element)
+
+template <bool TA, bool TB, bool BS>
 __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n, int nk)
 {
     extern __shared__ double smem[];
@@ -82,6 +89,7 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     const unsigned long long sgnA = neg ? 0x8000000000000000ull : 0ull;
     const int a_off = (wave * 16 + fmu) * 4 + fcomp;      // + kk*A_LD + 16*m
     const int b_off = fc * B_PL + (lane & 15);            // + kk*4*B_PL + 16*n
+    const unsigned conjB = p.conjB ? 0x80000000u : 0u;     // sign bit of the high word of q1..q3
 
     d4 acc[4][4];
 #pragma unroll
@@ -92,63 +100,67 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     d2 ra[A_CHUNKS];
     d2 rb[B_QUATS][2];
 
+    // Staging coordinates of slot i (recomputed from the thread id where used,
+    // which is cheaper than keeping them live in registers): A chunk i holds
+    // half `half` of quaternion (mu, ka) of the tile, B slot i quaternion (nu, ka).
+    auto a_slot = [&](int i, int &mu, int &ka, int &half) {
+        const int q = tid + NT * i;
+        half = q & 1;
+        if (!TA) { mu = (q >> 1) % BM; ka = (q >> 1) / BM; }
+        else     { ka = (q >> 1) % BK; mu = (q >> 1) / BK; }
+    };
+    auto b_slot = [&](int i, int &nu, int &ka) {
+        const int q = tid + NT * i;
+        if (!TB) { ka = q % BK; nu = q / BK; }
+        else     { nu = q % BN; ka = q / BN; }
+    };
+
+    // fetch K-tile kt into registers; elements at or past K (and whole tiles past
+    // the end) and rows outside the matrix read as zero through the buffer range
+    // check (in-tile byte offsets are below 2^31, see f64_ld_supported)
     auto load_tile = [&](int kt) {
         const int k0 = kt * BK;
+        const int krem = p.K - k0;
+        const double *Ab = p.A + 4 * (TA ? ((int64_t)m0 * p.lda + k0) : ((int64_t)k0 * p.lda + m0));
+        const double *Bb = p.B + 4 * (TB ? ((int64_t)k0 * p.ldb + n0) : ((int64_t)n0 * p.ldb + k0));
+        const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, 0x7fffffff, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, 0x7fffffff, 0x00020000);
 #pragma unroll
         for (int i = 0; i < A_CHUNKS; ++i) {
-            const int q = tid + NT * i;
-            const int half = q & 1;
-            int mu, ka;
-            if (!TA) { mu = (q >> 1) % BM; ka = (q >> 1) / BM; }
-            else     { ka = (q >> 1) % BK; mu = (q >> 1) / BK; }
-            const int gm = m0 + mu, gk = k0 + ka;
-            if (gm < p.M && gk < p.K) {
-                const int64_t e = TA ? ((int64_t)gm * p.lda + gk) : ((int64_t)gk * p.lda + gm);
-                ra[i] = *reinterpret_cast<const d2 *>(p.A + 4 * e + 2 * half);
-            } else {
-                ra[i] = (d2){0.0, 0.0};
-            }
+            int mu, ka, half;
+            a_slot(i, mu, ka, half);
+            const unsigned e = TA ? (unsigned)mu * (unsigned)p.lda + ka : (unsigned)ka * (unsigned)p.lda + mu;
+            const unsigned o = (m0 + mu < p.M && ka < krem) ? 32u * e + 16u * half : kOob;
+            ra[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rA, o, 0, 0));
         }
 #pragma unroll
         for (int i = 0; i < B_QUATS; ++i) {
-            const int q = tid + NT * i;
             int nu, ka;
-            if (!TB) { ka = q % BK; nu = q / BK; }
-            else     { nu = q % BN; ka = q / BN; }
-            const int gn = n0 + nu, gk = k0 + ka;
-            if (gn < p.N && gk < p.K) {
-                const int64_t e = TB ? ((int64_t)gk * p.ldb + gn) : ((int64_t)gn * p.ldb + gk);
-                const d2 *src = reinterpret_cast<const d2 *>(p.B + 4 * e);
-                rb[i][0] = src[0];
-                rb[i][1] = src[1];
-            } else {
-                rb[i][0] = (d2){0.0, 0.0};
-                rb[i][1] = (d2){0.0, 0.0};
-            }
+            b_slot(i, nu, ka);
+            const unsigned e = TB ? (unsigned)ka * (unsigned)p.ldb + nu : (unsigned)nu * (unsigned)p.ldb + ka;
+            const bool ok = n0 + nu < p.N && ka < krem;
+            rb[i][0] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? 32u * e : kOob, 0, 0));
+            rb[i][1] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? 32u * e + 16u : kOob, 0, 0));
         }
     };
 
-    auto store_tile = [&](int stage) {
-        double *As = smem + stage * STAGE;
+    auto store_tile = [&](double *As) {
         double *Bs = As + A_STAGE;
 #pragma unroll
         for (int i = 0; i < A_CHUNKS; ++i) {
-            const int q = tid + NT * i;
-            const int half = q & 1;
-            int mu, ka;
-            if (!TA) { mu = (q >> 1) % BM; ka = (q >> 1) / BM; }
-            else     { ka = (q >> 1) % BK; mu = (q >> 1) / BK; }
+            int mu, ka, half;
+            a_slot(i, mu, ka, half);
             *reinterpret_cast<d2 *>(As + ka * A_LD + mu * 4 + 2 * half) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < B_QUATS; ++i) {
-            const int q = tid + NT * i;
             int nu, ka;
-            if (!TB) { ka = q % BK; nu = q / BK; }
-            else     { nu = q % BN; ka = q / BN; }
+            b_slot(i, nu, ka);
             double b[4] = {rb[i][0].x, rb[i][0].y, rb[i][1].x, rb[i][1].y};
-            if (p.conjB) { b[1] = -b[1]; b[2] = -b[2]; b[3] = -b[3]; }
-            if (p.has_bscale) {
+#pragma unroll
+            for (int c = 1; c < 4; ++c)
+                b[c] = __longlong_as_double(__double_as_longlong(b[c]) ^ ((long long)conjB << 32));
+            if constexpr (BS) {
                 double t[4];
                 qmul(p.bscale, b, t);
                 b[0] = t[0]; b[1] = t[1]; b[2] = t[2]; b[3] = t[3];
@@ -161,30 +173,49 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
         }
     };
 
-    if (nk > 0) {
-        load_tile(0);
-        store_tile(0);
-        __syncthreads();
-    }
-    for (int kt = 0; kt < nk; ++kt) {
-        const int stage = kt & 1;
-        if (kt + 1 < nk) load_tile(kt + 1);
-        const double *As = smem + stage * STAGE;
+    // Multiply the K-tile in stage `cur`; the registers holding the next K-tile
+    // are written into stage `nxt` half way through, so those LDS writes overlap
+    // the MFMAs.  Fragments of step kk + 1 are read while step kk's MFMAs run.
+    auto step_tile = [&](const double *As, double *Nxt) {
         const double *Bs = As + A_STAGE;
+        double a[2][4], b[2][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a[0][m] = As[a_off + 16 * m];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) b[0][n] = Bs[b_off + 16 * n];
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
-            double a[4], b[4];
+            const int cur = kk & 1;
+            if (kk + 1 < BK) {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) a[m] = flip(As[kk * A_LD + a_off + 16 * m], sgnA);
+                for (int m = 0; m < 4; ++m) a[cur ^ 1][m] = As[(kk + 1) * A_LD + a_off + 16 * m];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) b[n] = Bs[kk * 4 * B_PL + b_off + 16 * n];
+                for (int n = 0; n < 4; ++n) b[cur ^ 1][n] = Bs[(kk + 1) * 4 * B_PL + b_off + 16 * n];
+            }
+            // keep the sign flips of step kk + 1 out of this step: they would wait on the reads above
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+            for (int m = 0; m < 4; ++m) {
+                const double am = flip(a[cur][m], sgnA);
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (kk == BK - 3) store_tile(Nxt);
         }
-        if (kt + 1 < nk) store_tile(stage ^ 1);
+    };
+
+    if (nk > 0) {
+        load_tile(0);
+        store_tile(smem);
+        __syncthreads();
+    }
+    // tiles past the end load as zeros and land in the unused stage
+    for (int kt = 0; kt < nk; ++kt) {
+        const int st = kt & 1;
+        load_tile(kt + 1);
+        step_tile(smem + st * STAGE, smem + (st ^ 1) * STAGE);
         __syncthreads();
     }
 
@@ -217,12 +248,12 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     }
 }
 
-template <bool TA, bool TB>
+template <bool TA, bool TB, bool BS>
 hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB, BS>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -234,17 +265,24 @@ hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
     const int64_t nblocks = (int64_t)tiles_m * tiles_n;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,
+    hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB, BS>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,
                        d, tiles_m, tiles_n, nk);
     return hipGetLastError();
 }
 
 }  // namespace
 
+template <bool BS>
+hipError_t launch_ops(const GemmDesc<double> &d, hipStream_t stream)
+{
+    if (d.opA_t) return d.opB_t ? launch_t<true, true, BS>(d, stream) : launch_t<true, false, BS>(d, stream);
+    return d.opB_t ? launch_t<false, true, BS>(d, stream) : launch_t<false, false, BS>(d, stream);
+}
+
 hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream)
 {
-    if (d.opA_t) return d.opB_t ? launch_t<true, true>(d, stream) : launch_t<true, false>(d, stream);
-    return d.opB_t ? launch_t<false, true>(d, stream) : launch_t<false, false>(d, stream);
+    if (!f64_ld_supported(d.lda, d.ldb, d.opA_t, d.opB_t)) return hipErrorInvalidValue;
+    return d.has_bscale ? launch_ops<true>(d, stream) : launch_ops<false>(d, stream);
 }
 
 }  // namespace qg

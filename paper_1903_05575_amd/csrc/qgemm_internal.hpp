@@ -39,6 +39,16 @@ hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream);
 // (and the beta term) is written to that FP64 array instead of d.C.
 hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream);
 constexpr int kSplitPanel = 64;
+// Leading dimensions the FP64 tiles can address with 32-bit in-tile byte
+// offsets (64 x 64 x 8 quaternion tiles of 32 bytes; below 2^31 bytes).
+inline bool f64_ld_supported(int64_t lda, int64_t ldb, bool ta, bool tb)
+{
+    const int64_t lim = (int64_t)1 << 31;
+    const int64_t fa = 32 * (ta ? (64 * lda + 8) : (8 * lda + 64));
+    const int64_t fb = 32 * (tb ? (8 * ldb + 64) : (64 * ldb + 8));
+    return fa < lim && fb < lim;
+}
+
 // Leading dimensions the split-BF16 tiles can address with 32-bit in-tile
 // offsets (64 x 64 x 16 quaternion tiles; below 2^31 bytes).
 inline bool split_ld_supported(int64_t lda, int64_t ldb, bool ta, bool tb)
