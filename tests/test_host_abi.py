@@ -126,3 +126,10 @@ def test_split_unsupported_leading_dimension(L):
     assert rc == 5 and L.qgemm_last_invalid_arg() == 8
     rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, big * 4, ONE, FAKE, 4, 6, None)
     assert rc == 5 and L.qgemm_last_invalid_arg() == 10
+
+
+def test_f64_unsupported_leading_dimension(L):
+    """The FP64 tiles address a K-tile with 32-bit offsets: a transposed A with
+    lda >= 2^20 quaternions is refused as unsupported (host check)."""
+    rc = call_d(L, opA=1, lda=1 << 20)
+    assert rc == 5 and L.qgemm_last_invalid_arg() == 8
