@@ -12,12 +12,13 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    HBM traffic from the committed rocprofv3 counter summary when
                    it was taken on the current kernel source;
   cpu_baseline  -- the CPU oracle timed on this host on a bounded column sample;
-  variants      -- the split-BF16 FP32 path, the grouped batched launch and the
-                   linear-layer forward + backward, each with its own rate and
-                   its error against the oracle on sampled outputs.
+  variants      -- the split-BF16 FP32 path, the grouped batched launch, the
+                   linear-layer forward + backward and the general scalar
+                   placement, each with its own rate and its error against the
+                   oracle on sampled outputs.
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
-    python bench.py --only fp64|split|grouped|linear    one part, no CPU baseline
+    python bench.py --only fp64|split|grouped|linear|scalars    one part, no CPU baseline
 """
 import argparse
 import hashlib
@@ -236,6 +237,37 @@ def variant_linear(steps, warmup):
         "rel_err_dX_sampled": float(f"{relfro(dX[:, rows], dXs):.3e}")}}
 
 
+def variant_scalars(steps, warmup):
+    """General scalar placement (qgemm_ex_d): FP64 4096^3 N/N with left, middle
+    and right alpha and left and right beta, beside qgemm_d on the same data;
+    error on a 64 x 32 sample against the oracle's qgemm_ex."""
+    import oracle
+    n = 4096
+    p = W.gemm_problem(W.BASE_SEED + 5, n, n, n, "N", "N")
+    g = W.rng(W.BASE_SEED + 6)
+    aL, aM, aR, bL, bR = (g.uniform(-1, 1, 4) for _ in range(5))
+    A, B = dev(p["A"]), dev(p["B"])
+    C0 = dev(p["C"])
+    C = C0.clone()
+    _, ev = time_launches(lambda: q.qgemm_ex("N", "N", n, n, n, aL, aM, aR, A, n, B, n, bL, bR, C, n), steps, warmup)
+    C2 = C0.clone()
+    _, ev_d = time_launches(lambda: q.qgemm_d("N", "N", n, n, n, aL, A, n, B, n, bL, C2, n), steps, warmup)
+    C.copy_(C0)
+    q.qgemm_ex("N", "N", n, n, n, aL, aM, aR, A, n, B, n, bL, bR, C, n)
+    gs = np.random.default_rng(7)
+    rows = np.sort(gs.choice(n, 64, replace=False))
+    cols = np.sort(gs.choice(n, 32, replace=False))
+    Bs = np.ascontiguousarray(p["B"][cols])
+    Cs = np.ascontiguousarray(p["C"][cols][:, rows])
+    As = np.ascontiguousarray(p["A"][:, rows])
+    want = oracle.qgemm_ex("N", "N", 64, 32, n, aL, aM, aR, As, 64, Bs, n, bL, bR, Cs, 64)
+    got = C.cpu().numpy()[cols][:, rows]
+    fl = q.flops(n, n, n)
+    return {"fp64_ex_4096_all_scalars": {"ms": round(ev, 3), "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
+                                         "qgemm_d_same_data_ms": round(ev_d, 3),
+                                         "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}}
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -256,7 +288,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -271,8 +303,9 @@ def main():
         calibrate_copy()
         return
 
-    if args.only in ("split", "grouped", "linear"):
-        fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear}[args.only]
+    if args.only in ("split", "grouped", "linear", "scalars"):
+        fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
+              "scalars": variant_scalars}[args.only]
         print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
@@ -290,7 +323,7 @@ def main():
     fl = q.flops(n, n, n)
     value = fl / (wall_ms * 1e-3) / 1e12
     achieved = fl / (ev_ms * 1e-3) / 1e12
-    sha = source_sha("qgemm_f64.hip", "qgemm_internal.hpp")
+    sha = source_sha("qgemm_f64.hip", "qgemm_internal.hpp", "qgemm_device.hpp")
     traffic = read_traffic(f"qgemm_f64_{n}", sha)
     line = {
         "metric": METRIC,
@@ -321,7 +354,8 @@ def main():
         return
     if not args.no_variants:
         variants = {}
-        for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear)):
+        for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
+                         ("scalars", variant_scalars)):
             log(f"[bench] variant {name}")
             variants.update(fn(args.steps, args.warmup))
             torch.cuda.empty_cache()

@@ -123,6 +123,36 @@ qgemm_status_t qgemm_s_c64(int opA, int opB, int64_t M, int64_t N, int64_t K,
                            double *C, int64_t ldc, int split_terms, void *stream);
 
 /*
+ * qgemm_ex_d / qgemm_ex_s -- general scalar placement.  Because quaternion
+ * scalars do not commute with matrices, the left, right and middle scalar
+ * products differ (Sec. 2.2: qQ, Qq and PqQ).  These calls compute
+ *     C <- aL * ( sum_k op(A)_{mu k} * aM * op(B)_{k nu} ) * aR + bL * C * bR
+ * with aL = alpha_left, aM = alpha_mid, aR = alpha_right, bL = beta_left,
+ * bR = beta_right (host arrays of 4 doubles).  A NULL scalar takes its default:
+ * the unit quaternion for aL, aM, aR and bR, zero for bL.  With aM = aR = bR =
+ * unit this is qgemm_d / qgemm_s.  aM multiplies every element of op(B) (after
+ * the op) from the left as the tile is staged; aR and bR are applied in the
+ * epilogue.  Any of aL, aM, aR zero: the product is not formed (A, B not
+ * read); bL zero: C is not read.  Precision as qgemm_d (FP64) and qgemm_s
+ * (split-BF16, scalars applied in FP32; aM is applied to op(B) in FP32 before
+ * the split).
+ * Arguments: 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 alpha_left, 7 alpha_mid,
+ *   8 alpha_right, 9 A, 10 lda, 11 B, 12 ldb, 13 beta_left, 14 beta_right,
+ *   15 C, 16 ldc, then (qgemm_ex_s only) 17 split_terms, then stream.
+ */
+qgemm_status_t qgemm_ex_d(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                          const double *alpha_left, const double *alpha_mid,
+                          const double *alpha_right, const double *A, int64_t lda,
+                          const double *B, int64_t ldb, const double *beta_left,
+                          const double *beta_right, double *C, int64_t ldc, void *stream);
+qgemm_status_t qgemm_ex_s(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                          const double *alpha_left, const double *alpha_mid,
+                          const double *alpha_right, const float *A, int64_t lda,
+                          const float *B, int64_t ldb, const double *beta_left,
+                          const double *beta_right, float *C, int64_t ldc,
+                          int split_terms, void *stream);
+
+/*
  * Grouped (batched) FP32 quaternion GEMM: many independent problems
  *   C_i <- alpha op(A_i) op(B_i) + beta C_i,  i = 0..count-1,
  * with common ops, scalars and split, run as ONE persistent kernel launch

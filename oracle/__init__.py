@@ -58,6 +58,9 @@ def lib():
                                             dp, dp, i64, dp, i64, dp, i64, dp,
                                             dp, i64, dp, i64, dp, i64]
         L.oracle_qgemm_backward.restype = ctypes.c_int
+        L.oracle_qgemm_ex.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, i64, dp, dp, dp,
+                                      dp, i64, dp, i64, dp, dp, dp, i64]
+        L.oracle_qgemm_ex.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_max_threads.argtypes = []
@@ -109,6 +112,20 @@ def qgemm(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc):
                             _ptr(B), ldb, _ptr(_f64(beta)), _ptr(out), ldc)
     if rc != 0:
         raise RuntimeError(f"oracle_qgemm failed ({rc})")
+    return out
+
+
+def qgemm_ex(opA, opB, M, N, K, aL, aM, aR, A, lda, B, ldb, bL, bR, C, ldc):
+    """Return aL (sum op(A) aM op(B)) aR + bL C bR as a new (N, ldc, 4) array
+    (general scalar placement); a scalar given as None is the default (unit,
+    or zero for bL)."""
+    A, B = _f64(A), _f64(B)
+    out = _f64(C).copy()
+    q = [None if x is None else _f64(x) for x in (aL, aM, aR, bL, bR)]
+    rc = lib().oracle_qgemm_ex(OPS[opA], OPS[opB], M, N, K, *[_ptr(x) for x in q[:3]], _ptr(A), lda,
+                               _ptr(B), ldb, _ptr(q[3]), _ptr(q[4]), _ptr(out), ldc)
+    if rc != 0:
+        raise RuntimeError(f"oracle_qgemm_ex failed ({rc})")
     return out
 
 

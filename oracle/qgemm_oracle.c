@@ -166,6 +166,67 @@ int oracle_qgemm(int opA, int opB, int64_t M, int64_t N, int64_t K,
     return failed ? -1 : 0;
 }
 
+/* General scalar placement (Sec. 2.2, left, right and middle scalar products
+ * (qQ)_{mu nu} = q Q_{mu nu}, (Qq)_{mu nu} = Q_{mu nu} q,
+ * (PqQ)_{mu nu} = sum_k P_{mu k} q Q_{k nu}):
+ *   C <- aL * ( sum_k op(A)_{mu k} * aM * op(B)_{k nu} ) * aR + bL * C * bR.
+ * Each of aL, aM, aR, bR may be NULL, meaning the unit quaternion; bL may be
+ * NULL, meaning zero.  Written as plain loops in the order of the formula:
+ * for every output element the middle scalar multiplies op(B) from the left,
+ * the product op(A) (aM op(B)) is summed over k, and the outer scalars are
+ * applied on their sides.  Same quick-return rules as oracle_qgemm (bL zero:
+ * C not read; aL or aM or aR zero, or K == 0: the sum is not formed). */
+int oracle_qgemm_ex(int opA, int opB, int64_t M, int64_t N, int64_t K,
+                    const double *aL, const double *aM, const double *aR,
+                    const double *A, int64_t lda, const double *B, int64_t ldb,
+                    const double *bL, const double *bR, double *C, int64_t ldc)
+{
+    static const double one[4] = {1.0, 0.0, 0.0, 0.0};
+    static const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+    if (opA < 0 || opA > 3 || opB < 0 || opB > 3) return -2;
+    if (M <= 0 || N <= 0) return 0;
+    if (!aL) aL = one;
+    if (!aM) aM = one;
+    if (!aR) aR = one;
+    if (!bL) bL = zero;
+    if (!bR) bR = one;
+    const int bz = (bL[0] == 0.0 && bL[1] == 0.0 && bL[2] == 0.0 && bL[3] == 0.0);
+    const int az = (aL[0] == 0.0 && aL[1] == 0.0 && aL[2] == 0.0 && aL[3] == 0.0) ||
+                   (aM[0] == 0.0 && aM[1] == 0.0 && aM[2] == 0.0 && aM[3] == 0.0) ||
+                   (aR[0] == 0.0 && aR[1] == 0.0 && aR[2] == 0.0 && aR[3] == 0.0);
+    if (az) K = 0;
+    double *opa = materialise_op(opA, M, K, A, lda);
+    double *opb = materialise_op(opB, K, N, B, ldb);
+    if (!opa || !opb) { free(opa); free(opb); return -1; }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t nu = 0; nu < N; ++nu) {
+        for (int64_t mu = 0; mu < M; ++mu) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int64_t ka = 0; ka < K; ++ka) {
+                double mb[4], t[4];
+                oracle_hamilton(aM, opb + 4 * (ka + nu * K), mb);
+                oracle_hamilton(opa + 4 * (mu + ka * M), mb, t);
+                acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[3] += t[3];
+            }
+            double l[4], r[4], u[4] = {0.0, 0.0, 0.0, 0.0}, w[4];
+            oracle_hamilton(aL, acc, l);
+            oracle_hamilton(l, aR, r);
+            double *c = C + 4 * (mu + nu * ldc);
+            if (!bz) {
+                oracle_hamilton(bL, c, w);
+                oracle_hamilton(w, bR, u);
+            }
+            c[0] = r[0] + u[0];
+            c[1] = r[1] + u[1];
+            c[2] = r[2] + u[2];
+            c[3] = r[3] + u[3];
+        }
+    }
+    free(opa);
+    free(opb);
+    return 0;
+}
+
 /* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *   C = alpha op(A) op(B) + beta C0.

@@ -9,8 +9,8 @@ Storage: a rows x cols quaternion matrix with leading dimension ld is a
 contiguous tensor of shape (cols, ld, 4): column-major, four interleaved
 components (q0, q1, q2, q3) per element.
 """
-from ._lib import (QGemmError, GroupedPlan, TILE_CLASSES, lib, qgemm_d, qgemm_s, qgemm_backward,  # noqa: F401
-                   exported_symbols)
+from ._lib import (QGemmError, GroupedPlan, TILE_CLASSES, lib, qgemm_d, qgemm_s, qgemm_ex,  # noqa: F401
+                   qgemm_backward, exported_symbols)
 from .autograd import QGemmFn, QLinear, qgemm  # noqa: F401
 
 

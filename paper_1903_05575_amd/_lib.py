@@ -46,6 +46,10 @@ _SIGNATURES = {
     "qgemm_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemm_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
     "qgemm_s_c64": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _int, _vp], _int),
+    "qgemm_ex_d": ([_int, _int, _i64, _i64, _i64, _dp, _dp, _dp, _vp, _i64, _vp, _i64, _dp, _dp, _vp, _i64,
+                    _vp], _int),
+    "qgemm_ex_s": ([_int, _int, _i64, _i64, _i64, _dp, _dp, _dp, _vp, _i64, _vp, _i64, _dp, _dp, _vp, _i64,
+                    _int, _vp], _int),
     "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
                                    _int, _int], _int),
     "qgemm_batched_run": ([_vp, _vp], _int),
@@ -251,3 +255,35 @@ class GroupedPlan:
             self.close()
         except Exception:
             pass
+
+
+def _q4_opt(x):
+    if x is None:
+        return None, None
+    return _q4(x)
+
+
+def qgemm_ex(opA, opB, M, N, K, alpha_left, alpha_mid, alpha_right, A, lda, B, ldb, beta_left, beta_right,
+             C, ldc, split_terms=6, stream=None):
+    """C <- aL (sum op(A) aM op(B)) aR + bL C bR (C-ABI qgemm_ex_d for float64
+    tensors, qgemm_ex_s for float32).  A scalar given as None takes its default
+    (unit; zero for beta_left)."""
+    dtype = C.dtype
+    ra, ca = _stored(opA, M, K)
+    rb, cb = _stored(opB, K, N)
+    if M and N and K:
+        _check_storage(A, ra, ca, lda, dtype, "A")
+        _check_storage(B, rb, cb, ldb, dtype, "B")
+    _check_storage(C, M, N, ldc, dtype, "C")
+    q = [_q4_opt(x) for x in (alpha_left, alpha_mid, alpha_right, beta_left, beta_right)]
+    ptrs = [x[0] for x in q]
+    args = [OPS[opA], OPS[opB], M, N, K, ptrs[0], ptrs[1], ptrs[2], _ptr(A), lda, _ptr(B), ldb, ptrs[3], ptrs[4],
+            _ptr(C), ldc]
+    if dtype == torch.float64:
+        rc = lib().qgemm_ex_d(*args, _stream(stream))
+        _raise(rc, "qgemm_ex_d")
+    elif dtype == torch.float32:
+        rc = lib().qgemm_ex_s(*args, int(split_terms), _stream(stream))
+        _raise(rc, "qgemm_ex_s")
+    else:
+        raise ValueError(f"unsupported dtype {dtype}")

@@ -83,10 +83,13 @@ qg::GemmDesc<T> make_desc(int opA, int opB, int64_t M, int64_t N, int64_t K, con
     d.has_bscale = false;
     d.store_t = false;
     d.store_conj = false;
+    d.has_right = false;
     for (int i = 0; i < 4; ++i) {
         d.alpha[i] = alpha[i];
         d.beta[i] = beta[i];
         d.bscale[i] = i == 0 ? 1.0 : 0.0;
+        d.alpha_r[i] = i == 0 ? 1.0 : 0.0;
+        d.beta_r[i] = i == 0 ? 1.0 : 0.0;
     }
     return d;
 }
@@ -197,6 +200,52 @@ qgemm_status_t backward_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, 
     return QGEMM_OK;
 }
 
+bool is_one4(const double *q) { return q[0] == 1.0 && q[1] == 0.0 && q[2] == 0.0 && q[3] == 0.0; }
+
+// General scalar placement C <- aL (sum op(A) aM op(B)) aR + bL C bR (the left,
+// middle and right scalar products of Sec. 2.2).  NULL scalars take their
+// defaults (unit; zero for bL).  Argument numbering of the public calls:
+// 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 aL, 7 aM, 8 aR, 9 A, 10 lda, 11 B, 12 ldb,
+// 13 bL, 14 bR, 15 C, 16 ldc, 17 split_terms (FP32 only).
+template <typename T>
+qgemm_status_t ex_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *aL, const double *aM,
+                       const double *aR, const T *A, int64_t lda, const T *B, int64_t ldb, const double *bL,
+                       const double *bR, T *C, int64_t ldc, int split_terms, hipStream_t stream)
+{
+    static const double one[4] = {1.0, 0.0, 0.0, 0.0};
+    static const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+    const double *l = aL ? aL : one, *m = aM ? aM : one, *r = aR ? aR : one;
+    const double *bl = bL ? bL : zero, *br = bR ? bR : one;
+    // the product vanishes when any alpha is zero: validate as for alpha = 0
+    const bool az = is_zero4(l) || is_zero4(m) || is_zero4(r);
+    qgemm_status_t s = validate(opA, opB, M, N, K, az ? zero : l, A, lda, B, ldb, bl, C, ldc, 4 * sizeof(T));
+    if (s != QGEMM_OK) {
+        static const int remap[14] = {0, 1, 2, 3, 4, 5, 6, 9, 10, 11, 12, 13, 15, 16};
+        g_bad_arg = remap[g_bad_arg];
+        return s;
+    }
+    if (sizeof(T) == 4) {
+        if (split_terms == 0) split_terms = 6;
+        if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 17);
+    }
+    if (M == 0 || N == 0) return QGEMM_OK;
+    const bool ld_ok = sizeof(T) == 4 ? qg::split_ld_supported(lda, ldb, op_transposes(opA), op_transposes(opB))
+                                      : qg::f64_ld_supported(lda, ldb, op_transposes(opA), op_transposes(opB));
+    if (!ld_ok) return fail(QGEMM_ERR_UNSUPPORTED, op_transposes(opA) ? 10 : 12);
+    auto d = make_desc<T>(opA, opB, M, N, K, az ? zero : l, A, lda, B, ldb, bl, C, ldc);
+    d.has_bscale = !az && !is_one4(m);
+    d.has_right = !(is_one4(r) && is_one4(br));
+    for (int i = 0; i < 4; ++i) {
+        d.bscale[i] = m[i];
+        d.alpha_r[i] = r[i];
+        d.beta_r[i] = br[i];
+    }
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) e = qg::launch_qgemm_f64(d, stream);
+    else e = qg::launch_qgemm_bf16x3(d, nullptr, split_terms, qg::kSplitPanel, stream);
+    return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -259,6 +308,24 @@ qgemm_status_t qgemm_s_c64(int opA, int opB, int64_t M, int64_t N, int64_t K, co
                            double *C, int64_t ldc, int split_terms, void *stream)
 {
     return split_common(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, nullptr, C, ldc, split_terms, stream);
+}
+
+qgemm_status_t qgemm_ex_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha_left,
+                          const double *alpha_mid, const double *alpha_right, const double *A, int64_t lda,
+                          const double *B, int64_t ldb, const double *beta_left, const double *beta_right,
+                          double *C, int64_t ldc, void *stream)
+{
+    return ex_impl<double>(opA, opB, M, N, K, alpha_left, alpha_mid, alpha_right, A, lda, B, ldb, beta_left,
+                           beta_right, C, ldc, 6, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qgemm_ex_s(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha_left,
+                          const double *alpha_mid, const double *alpha_right, const float *A, int64_t lda,
+                          const float *B, int64_t ldb, const double *beta_left, const double *beta_right,
+                          float *C, int64_t ldc, int split_terms, void *stream)
+{
+    return ex_impl<float>(opA, opB, M, N, K, alpha_left, alpha_mid, alpha_right, A, lda, B, ldb, beta_left,
+                          beta_right, C, ldc, split_terms, static_cast<hipStream_t>(stream));
 }
 
 qgemm_status_t qgemm_backward_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,

@@ -359,12 +359,20 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                                          tot[m][n][4 * j + 3]};
                     double o[4];
                     qmul(p.alpha, v, o);
+                    if (p.has_right) {
+                        const double t[4] = {o[0], o[1], o[2], o[3]};
+                        qmul(t, p.alpha_r, o);
+                    }
                     if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
                     double *dst = c64 + 4 * e;
                     if (!beta_zero) {
                         const double cq[4] = {dst[0], dst[1], dst[2], dst[3]};
                         double u[4];
                         qmul(p.beta, cq, u);
+                        if (p.has_right) {
+                            const double t[4] = {u[0], u[1], u[2], u[3]};
+                            qmul(t, p.beta_r, u);
+                        }
                         o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                     }
                     dst[0] = o[0]; dst[1] = o[1]; dst[2] = o[2]; dst[3] = o[3];
@@ -374,6 +382,11 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                                         tot[m][n][4 * j + 3]};
                     float o[4];
                     qmul(al, v, o);
+                    if (p.has_right) {
+                        const float ar[4] = {(float)p.alpha_r[0], (float)p.alpha_r[1], (float)p.alpha_r[2], (float)p.alpha_r[3]};
+                        const float t[4] = {o[0], o[1], o[2], o[3]};
+                        qmul(t, ar, o);
+                    }
                     if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
                     f32x4 *dst = reinterpret_cast<f32x4 *>(p.C + 4 * e);
                     if (!beta_zero) {
@@ -382,6 +395,11 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                         const float cq[4] = {c.x, c.y, c.z, c.w};
                         float u[4];
                         qmul(be, cq, u);
+                        if (p.has_right) {
+                            const float br[4] = {(float)p.beta_r[0], (float)p.beta_r[1], (float)p.beta_r[2], (float)p.beta_r[3]};
+                            const float t[4] = {u[0], u[1], u[2], u[3]};
+                            qmul(t, br, u);
+                        }
                         o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                     }
                     *dst = (f32x4){o[0], o[1], o[2], o[3]};

@@ -1,0 +1,50 @@
+// Device helpers shared by the GEMM kernels of libqgemm.so (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace qg {
+
+// 32-bit lane-constant sign mask of row r / column c of the real 4x4
+// left-multiplication block L(a) with vec(a b) = L(a) vec(b):
+//   L(a) = [[a0,-a1,-a2,-a3],[a1,a0,-a3,a2],[a2,a3,a0,-a1],[a3,-a2,a1,a0]]
+// derived from Eq. quaternion_prod.  Entry (r, c) equals
+// sign(r, c) * a[r ^ c]; bit 4r+c of kLNegMask is set where sign is -1.
+constexpr unsigned kLNegMask = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 6) | (1u << 11) | (1u << 13);
+
+__host__ __device__ inline bool l_negative(int r, int c) { return (kLNegMask >> (4 * r + c)) & 1u; }
+
+// Hamilton product p q on the device (Eq. quaternion_prod), used by the
+// epilogue for the left scalars.  Kept separate from any CPU reference.
+template <typename T>
+__device__ __forceinline__ void qmul(const T p[4], const T q[4], T out[4])
+{
+    out[0] = p[0] * q[0] - p[1] * q[1] - p[2] * q[2] - p[3] * q[3];
+    out[1] = p[0] * q[1] + p[1] * q[0] + p[2] * q[3] - p[3] * q[2];
+    out[2] = p[0] * q[2] - p[1] * q[3] + p[2] * q[0] + p[3] * q[1];
+    out[3] = p[0] * q[3] + p[1] * q[2] - p[2] * q[1] + p[3] * q[0];
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the MI355X (block b
+// runs on XCD b % 8, each XCD with its own L2).  Renumber so that every XCD
+// owns one contiguous range of tile ids, then raster those ids in groups of
+// `group` tile rows so neighbouring tiles on one XCD share A and B panels.
+__device__ __forceinline__ void xcd_tile(int bid, int nblocks, int tiles_m, int tiles_n,
+                                         int group, int &tm, int &tn)
+{
+    const int xcd = bid & 7;
+    const int local = bid >> 3;
+    const int per = nblocks >> 3;
+    const int rem = nblocks & 7;
+    const int id = (xcd < rem) ? xcd * (per + 1) + local
+                               : rem * (per + 1) + (xcd - rem) * per + local;
+    const int gsz = group * tiles_n;
+    const int g = id / gsz;
+    const int first_m = g * group;
+    const int gm = min(tiles_m - first_m, group);
+    const int within = id - g * gsz;
+    tm = first_m + within % gm;
+    tn = within / gm;
+}
+
+}  // namespace qg

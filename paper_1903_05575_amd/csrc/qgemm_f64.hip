@@ -231,6 +231,10 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
                 const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
                 double o[4];
                 qmul(p.alpha, v, o);
+                if (p.has_right) {
+                    const double t[4] = {o[0], o[1], o[2], o[3]};
+                    qmul(t, p.alpha_r, o);
+                }
                 if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
                 const int64_t e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
                 d2 *dst = reinterpret_cast<d2 *>(p.C + 4 * e);
@@ -239,6 +243,10 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
                     const double cq[4] = {c0.x, c0.y, c1.x, c1.y};
                     double u[4];
                     qmul(p.beta, cq, u);
+                    if (p.has_right) {
+                        const double t[4] = {u[0], u[1], u[2], u[3]};
+                        qmul(t, p.beta_r, u);
+                    }
                     o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                 }
                 dst[0] = (d2){o[0], o[1]};

@@ -84,11 +84,14 @@ __global__ __launch_bounds__(split::NT, kBlocksPerCU) void grouped_kernel(const 
         d.has_bscale = false;
         d.store_t = false;
         d.store_conj = false;
+        d.has_right = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             d.alpha[i] = s.alpha[i];
             d.beta[i] = s.beta[i];
             d.bscale[i] = 0.0;
+            d.alpha_r[i] = 0.0;
+            d.beta_r[i] = 0.0;
         }
         const int nk = alpha_zero ? 0 : (pr.K + kBK - 1) / kBK;
         switch (it.w) {

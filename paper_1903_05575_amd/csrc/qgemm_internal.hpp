@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/qgemm.h"
+#include "qgemm_device.hpp"
 
 namespace qg {
 
@@ -16,6 +17,8 @@ namespace qg {
 //   bscale        : optional left scalar s applied to every element of op(B),
 //                   i.e. the product op(A) (s op(B)) (the "middle scalar"
 //                   form P q Q of Sec. 2.2)
+//   alpha_r, beta_r : scalars multiplying from the right (the Q q form of
+//                   Sec. 2.2), applied in the epilogue when has_right
 //   store_t / store_conj : write the result transposed and/or conjugated
 //                   (used by the gradient to map d op(X) back to dX)
 template <typename T>
@@ -27,9 +30,12 @@ struct GemmDesc {
     int M, N, K;
     bool opA_t, conjA, opB_t, conjB;
     bool has_bscale, store_t, store_conj;
+    bool has_right;        // alpha_r / beta_r are not both the unit quaternion
     double alpha[4];
     double beta[4];
     double bscale[4];
+    double alpha_r[4];     // right scalars: C <- alpha acc alpha_r + beta C beta_r
+    double beta_r[4];
 };
 
 // Launch helpers (return a hipError_t from the launch).
@@ -72,47 +78,5 @@ void grouped_plan_info(const GroupedPlan *pl, int64_t *nitems, int *grid, int64_
 template <typename T>
 hipError_t launch_scale_left(const T *X, int64_t ldx, T *Y, int64_t ldy, int M, int N, const double s[4],
                              hipStream_t stream);
-
-// 32-bit lane-constant sign mask of row r / column c of the real 4x4
-// left-multiplication block L(a) with vec(a b) = L(a) vec(b):
-//   L(a) = [[a0,-a1,-a2,-a3],[a1,a0,-a3,a2],[a2,a3,a0,-a1],[a3,-a2,a1,a0]]
-// derived from Eq. quaternion_prod.  Entry (r, c) equals
-// sign(r, c) * a[r ^ c]; bit 4r+c of kLNegMask is set where sign is -1.
-constexpr unsigned kLNegMask = (1u << 1) | (1u << 2) | (1u << 3) | (1u << 6) | (1u << 11) | (1u << 13);
-
-__host__ __device__ inline bool l_negative(int r, int c) { return (kLNegMask >> (4 * r + c)) & 1u; }
-
-// Hamilton product p q on the device (Eq. quaternion_prod), used by the
-// epilogue for the left scalars.  Kept separate from any CPU reference.
-template <typename T>
-__device__ __forceinline__ void qmul(const T p[4], const T q[4], T out[4])
-{
-    out[0] = p[0] * q[0] - p[1] * q[1] - p[2] * q[2] - p[3] * q[3];
-    out[1] = p[0] * q[1] + p[1] * q[0] + p[2] * q[3] - p[3] * q[2];
-    out[2] = p[0] * q[2] - p[1] * q[3] + p[2] * q[0] + p[3] * q[1];
-    out[3] = p[0] * q[3] + p[1] * q[2] - p[2] * q[1] + p[3] * q[0];
-}
-
-// Blocks are dispatched round-robin over the 8 XCDs of the MI355X (block b
-// runs on XCD b % 8, each XCD with its own L2).  Renumber so that every XCD
-// owns one contiguous range of tile ids, then raster those ids in groups of
-// `group` tile rows so neighbouring tiles on one XCD share A and B panels.
-__device__ __forceinline__ void xcd_tile(int bid, int nblocks, int tiles_m, int tiles_n,
-                                         int group, int &tm, int &tn)
-{
-    const int xcd = bid & 7;
-    const int local = bid >> 3;
-    const int per = nblocks >> 3;
-    const int rem = nblocks & 7;
-    const int id = (xcd < rem) ? xcd * (per + 1) + local
-                               : rem * (per + 1) + (xcd - rem) * per + local;
-    const int gsz = group * tiles_n;
-    const int g = id / gsz;
-    const int first_m = g * group;
-    const int gm = min(tiles_m - first_m, group);
-    const int within = id - g * gsz;
-    tm = first_m + within % gm;
-    tn = within / gm;
-}
 
 }  // namespace qg

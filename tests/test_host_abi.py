@@ -133,3 +133,19 @@ def test_f64_unsupported_leading_dimension(L):
     lda >= 2^20 quaternions is refused as unsupported (host check)."""
     rc = call_d(L, opA=1, lda=1 << 20)
     assert rc == 5 and L.qgemm_last_invalid_arg() == 8
+
+
+def test_validation_ex(L):
+    """qgemm_ex_* argument numbering: 9 A, 10 lda, 11 B, 12 ldb, 15 C, 16 ldc, 17 split."""
+    n = None
+    rc = L.qgemm_ex_d(0, 0, 4, 4, 4, ONE, n, n, FAKE, 3, FAKE, 4, ONE, n, FAKE, 4, n)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 10
+    rc = L.qgemm_ex_d(0, 0, 4, 4, 4, n, n, n, FAKE, 4, FAKE, 4, n, n, FAKE + 8, 4, n)
+    assert rc == 2 and L.qgemm_last_invalid_arg() == 15
+    rc = L.qgemm_ex_d(0, 0, 4, 4, 4, n, n, n, FAKE, 4, FAKE, 4, n, n, FAKE, 2, n)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 16
+    rc = L.qgemm_ex_s(0, 0, 4, 4, 4, n, n, n, FAKE, 4, FAKE, 4, n, n, FAKE, 4, 7, n)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 17
+    # a zero middle scalar: A and B are not read, so NULL is accepted (N = 0: nothing launched)
+    rc = L.qgemm_ex_d(0, 0, 4, 0, 4, n, q4(0, 0, 0, 0), n, None, 4, None, 4, n, n, FAKE, 4, n)
+    assert rc == 0

@@ -335,6 +335,70 @@ def test_sampled_entries_helper():
             np.testing.assert_allclose(part, full[cols][:, rows], rtol=0, atol=1e-14)
 
 
+# ---------------------------------------------------------------- general scalar placement
+def _bf_ex(opA, opB, M, N, K, aL, aM, aR, A, B, bL, bR, C):
+    a = qref.apply_op(opA, A, M, K)
+    b = qref.apply_op(opB, B, K, N)
+    out = np.zeros((M, N, 4))
+    for mu in range(M):
+        for nu in range(N):
+            acc = [0.0] * 4
+            for ka in range(K):
+                t = qref.bf_mul(a[mu, ka], qref.bf_mul(aM, b[ka, nu]))
+                acc = [acc[c] + t[c] for c in range(4)]
+            l = qref.bf_mul(qref.bf_mul(aL, acc), aR)
+            r = qref.bf_mul(qref.bf_mul(bL, C[mu, nu]), bR)
+            out[mu, nu] = [l[c] + r[c] for c in range(4)]
+    return out
+
+
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C"), ("C", "R"), ("R", "T")])
+def test_scalar_placement_brute_force(opA, opB):
+    M, N, K = 3, 4, 5
+    p = W.gemm_problem(700 + "NTCR".index(opA) * 4 + "NTCR".index(opB), M, N, K, opA, opB, dist="normal", pad=1)
+    g = W.rng(9)
+    aL, aM, aR, bL, bR = (g.standard_normal(4) for _ in range(5))
+    got = oracle.qgemm_ex(opA, opB, M, N, K, aL, aM, aR, p["A"], p["lda"], p["B"], p["ldb"], bL, bR,
+                          p["C"], p["ldc"])
+    want = _bf_ex(opA, opB, M, N, K, aL, aM, aR, p["A"], p["B"], bL, bR, qref.logical(p["C"], M, N))
+    np.testing.assert_allclose(qref.logical(got, M, N), want, atol=1e-12)
+
+
+def test_scalar_placement_complex_embedding():
+    """aL A (aM I) B aR + bL C bR through complex128 products on the block
+    representation: scalar matrices qI embed as block scalar matrices, and a
+    middle or right scalar is a matrix product like any other (Sec. 2.2)."""
+    M, N, K = 6, 5, 7
+    p = W.gemm_problem(71, M, N, K, "N", "N", dist="normal")
+    g = W.rng(10)
+    aL, aM, aR, bL, bR = (g.standard_normal(4) for _ in range(5))
+    got = qref.logical(oracle.qgemm_ex("N", "N", M, N, K, aL, aM, aR, p["A"], p["lda"], p["B"], p["ldb"],
+                                       bL, bR, p["C"], p["ldc"]), M, N)
+    Ac = qref.complex_rep_block(qref.logical(p["A"], M, K))
+    Bc = qref.complex_rep_block(qref.logical(p["B"], K, N))
+    Cc = qref.complex_rep_block(qref.logical(p["C"], M, N))
+    S = qref.scalar_block
+    want = S(aL, M) @ Ac @ S(aM, K) @ Bc @ S(aR, N) + S(bL, M) @ Cc @ S(bR, N)
+    np.testing.assert_allclose(qref.complex_rep_block(got), want, atol=1e-12)
+
+
+def test_scalar_placement_reduces_to_left_form_and_differs():
+    """Unit middle/right scalars give qgemm; moving a scalar changes the result
+    (qPQ != PqQ != PQq, Sec. 2.2)."""
+    M, N, K = 4, 3, 5
+    p = W.gemm_problem(72, M, N, K, "N", "N", dist="normal")
+    q = np.array([0.3, 0.9, -0.4, 0.2])
+    left = oracle.qgemm_ex("N", "N", M, N, K, q, None, None, p["A"], p["lda"], p["B"], p["ldb"],
+                           p["beta"], None, p["C"], p["ldc"])
+    ref = oracle.qgemm("N", "N", M, N, K, q, p["A"], p["lda"], p["B"], p["ldb"], p["beta"], p["C"], p["ldc"])
+    np.testing.assert_allclose(left, ref, atol=1e-13)
+    mid = oracle.qgemm_ex("N", "N", M, N, K, None, q, None, p["A"], p["lda"], p["B"], p["ldb"],
+                          p["beta"], None, p["C"], p["ldc"])
+    right = oracle.qgemm_ex("N", "N", M, N, K, None, None, q, p["A"], p["lda"], p["B"], p["ldb"],
+                            p["beta"], None, p["C"], p["ldc"])
+    assert np.abs(left - mid).max() > 1e-2 and np.abs(mid - right).max() > 1e-2 and np.abs(left - right).max() > 1e-2
+
+
 # ---------------------------------------------------------------- gradient
 def _loss(opA, opB, M, N, K, al, A, lda, B, ldb, G, be, C0):
     out = oracle.qgemm(opA, opB, M, N, K, al, A, lda, B, ldb, be, C0, M)
