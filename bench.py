@@ -13,12 +13,12 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    it was taken on the current kernel source;
   cpu_baseline  -- the CPU oracle timed on this host on a bounded column sample;
   variants      -- the split-BF16 FP32 path, the grouped batched launch, the
-                   linear-layer forward + backward and the general scalar
-                   placement, each with its own rate and its error against the
-                   oracle on sampled outputs.
+                   linear-layer forward + backward, the general scalar
+                   placement and the Hermitian rank-k update, each with its own
+                   rate and its error against the oracle on sampled outputs.
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
-    python bench.py --only fp64|split|grouped|linear|scalars    one part, no CPU baseline
+    python bench.py --only fp64|split|grouped|linear|scalars|herk    one part, no CPU baseline
 """
 import argparse
 import hashlib
@@ -268,6 +268,31 @@ def variant_scalars(steps, warmup):
                                          "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}}
 
 
+def variant_herk(steps, warmup):
+    """Hermitian rank-k update qherk_d: lower triangle of C <- alpha A A^H + beta C,
+    N = K = 8192 FP64 (alpha = 1, beta = 0.5); effective flops 32 K N (N + 1) / 2;
+    error on sampled lower-triangle entries against the oracle."""
+    import oracle
+    n = 8192
+    g = W.rng(W.BASE_SEED + 7)
+    A = W.qmatrix(g, n, n, dist="uniform")
+    C = W.qmatrix(g, n, n, dist="uniform")
+    Ad, Cd0 = dev(A), dev(C)
+    Cd = Cd0.clone()
+    _, ev = time_launches(lambda: q.qherk("L", "N", n, n, 1.0, Ad, n, 0.5, Cd, n), steps, warmup)
+    Cd.copy_(Cd0)
+    q.qherk("L", "N", n, n, 1.0, Ad, n, 0.5, Cd, n)
+    gs = np.random.default_rng(8)
+    cols = np.sort(gs.choice(n // 2, 16, replace=False))
+    rows = np.sort(gs.choice(np.arange(n // 2 + 1, n), 64, replace=False))   # strictly below the diagonal
+    want = oracle.qgemm_entries("N", "C", n, np.array([1.0, 0, 0, 0]), A, A, np.array([0.5, 0, 0, 0]), C, rows, cols)
+    got = Cd.cpu().numpy()[cols][:, rows]
+    fl = 32 * n * n * (n + 1) // 2
+    return {"fp64_herk_8192_lower": {"ms": round(ev, 3), "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
+                                     "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4),
+                                     "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}}
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -288,7 +313,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -303,9 +328,9 @@ def main():
         calibrate_copy()
         return
 
-    if args.only in ("split", "grouped", "linear", "scalars"):
+    if args.only in ("split", "grouped", "linear", "scalars", "herk"):
         fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
-              "scalars": variant_scalars}[args.only]
+              "scalars": variant_scalars, "herk": variant_herk}[args.only]
         print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
@@ -355,7 +380,7 @@ def main():
     if not args.no_variants:
         variants = {}
         for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
-                         ("scalars", variant_scalars)):
+                         ("scalars", variant_scalars), ("herk", variant_herk)):
             log(f"[bench] variant {name}")
             variants.update(fn(args.steps, args.warmup))
             torch.cuda.empty_cache()

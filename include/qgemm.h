@@ -63,6 +63,11 @@ typedef enum {
 } qgemm_op_t;
 
 typedef enum {
+    QGEMM_LOWER = 0,
+    QGEMM_UPPER = 1
+} qgemm_uplo_t;
+
+typedef enum {
     QGEMM_OK = 0,
     QGEMM_ERR_INVALID_ARG = 1,
     QGEMM_ERR_MISALIGNED = 2,
@@ -151,6 +156,28 @@ qgemm_status_t qgemm_ex_s(int opA, int opB, int64_t M, int64_t N, int64_t K,
                           const float *B, int64_t ldb, const double *beta_left,
                           const double *beta_right, float *C, int64_t ldc,
                           int split_terms, void *stream);
+
+/*
+ * qherk_d / qherk_s -- Hermitian rank-k update (one of the BLAS-3 operations
+ * the paper's GEMM kernels are meant to serve, Sec. 3; quaternion
+ * Hermiticity Q = Q^H, Sec. 2.2), in the BLAS HERK convention:
+ *     trans = QGEMM_OP_N:  C <- alpha A A^H + beta C,   A is N x K
+ *     trans = QGEMM_OP_C:  C <- alpha A^H A + beta C,   A is K x N
+ * alpha and beta are real.  Only the triangle `uplo` (QGEMM_LOWER: mu >= nu,
+ * QGEMM_UPPER: mu <= nu) of the N x N matrix C is read and written; the
+ * vector part of each diagonal element is set to zero (a Hermitian matrix
+ * has a real diagonal; the input's diagonal vector part is not used).
+ * Quick returns: N == 0, or (alpha == 0 or K == 0) with beta == 1, leave C
+ * untouched; beta == 0 never reads C.  About half the work of the GEMM.
+ * Arguments: 1 uplo, 2 trans, 3 N, 4 K, 5 alpha, 6 A, 7 lda, 8 beta, 9 C,
+ *   10 ldc, then (qherk_s only) 11 split_terms, then stream.
+ */
+qgemm_status_t qherk_d(int uplo, int trans, int64_t N, int64_t K, double alpha,
+                       const double *A, int64_t lda, double beta, double *C, int64_t ldc,
+                       void *stream);
+qgemm_status_t qherk_s(int uplo, int trans, int64_t N, int64_t K, double alpha,
+                       const float *A, int64_t lda, double beta, float *C, int64_t ldc,
+                       int split_terms, void *stream);
 
 /*
  * Grouped (batched) FP32 quaternion GEMM: many independent problems

@@ -61,6 +61,9 @@ def lib():
         L.oracle_qgemm_ex.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, i64, dp, dp, dp,
                                       dp, i64, dp, i64, dp, dp, dp, i64]
         L.oracle_qgemm_ex.restype = ctypes.c_int
+        L.oracle_qherk.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, ctypes.c_double, dp, i64,
+                                   ctypes.c_double, dp, i64]
+        L.oracle_qherk.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_max_threads.argtypes = []
@@ -126,6 +129,19 @@ def qgemm_ex(opA, opB, M, N, K, aL, aM, aR, A, lda, B, ldb, bL, bR, C, ldc):
                                _ptr(B), ldb, _ptr(q[3]), _ptr(q[4]), _ptr(out), ldc)
     if rc != 0:
         raise RuntimeError(f"oracle_qgemm_ex failed ({rc})")
+    return out
+
+
+def qherk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
+    """Hermitian rank-k update on the triangle uplo ('L' or 'U') of C:
+    alpha op(A) op(A)^H + beta C with op = trans ('N' or 'C'), alpha and beta
+    real.  Returns a new (n, ldc, 4) array."""
+    A = _f64(A)
+    out = _f64(C).copy()
+    rc = lib().oracle_qherk({"L": 0, "U": 1}[uplo], OPS[trans], n, k, float(alpha), _ptr(A), lda,
+                            float(beta), _ptr(out), ldc)
+    if rc != 0:
+        raise RuntimeError(f"oracle_qherk failed ({rc})")
     return out
 
 

@@ -227,6 +227,45 @@ int oracle_qgemm_ex(int opA, int opB, int64_t M, int64_t N, int64_t K,
     return 0;
 }
 
+/* Hermitian rank-k update (the rank-k update the GEMM kernels serve, Sec. 3;
+ * Hermitian: Q = Q^H, Sec. 2.2), a reading in the BLAS HERK convention:
+ *   trans = 0 (N): C <- alpha A A^H + beta C,  A is n x k (leading dim lda)
+ *   trans = 2 (C): C <- alpha A^H A + beta C,  A is k x n
+ * alpha and beta are real.  Only the triangle uplo (0 lower: mu >= nu,
+ * 1 upper: mu <= nu) of C is read or written.  The diagonal of a Hermitian
+ * matrix is real: its vector part is set to zero in the result (C's diagonal
+ * vector part is not read).  beta == 0: C is not read; alpha == 0 or k == 0:
+ * the product is not formed, and with beta == 1 as well C is left as it is
+ * (the BLAS quick return).  Plain loops over the triangle. */
+int oracle_qherk(int uplo, int trans, int64_t n, int64_t k, double alpha, const double *A, int64_t lda,
+                 double beta, double *C, int64_t ldc)
+{
+    if ((uplo != 0 && uplo != 1) || (trans != 0 && trans != 2)) return -2;
+    if (n <= 0) return 0;
+    if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;   /* nothing to update (BLAS quick return) */
+    if (alpha == 0.0) k = 0;
+    double *opa = materialise_op(trans, n, k, A, lda);   /* op(A): n x k */
+    if (!opa) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t nu = 0; nu < n; ++nu) {
+        const int64_t lo = uplo == 0 ? nu : 0, hi = uplo == 0 ? n : nu + 1;
+        for (int64_t mu = lo; mu < hi; ++mu) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int64_t ka = 0; ka < k; ++ka) {
+                double cb[4], t[4];
+                conj_q(opa + 4 * (nu + ka * n), cb);
+                oracle_hamilton(opa + 4 * (mu + ka * n), cb, t);
+                acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[3] += t[3];
+            }
+            double *c = C + 4 * (mu + nu * ldc);
+            for (int i = 0; i < 4; ++i) c[i] = alpha * acc[i] + (beta == 0.0 ? 0.0 : beta * c[i]);
+            if (mu == nu) c[1] = c[2] = c[3] = 0.0;
+        }
+    }
+    free(opa);
+    return 0;
+}
+
 /* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *   C = alpha op(A) op(B) + beta C0.

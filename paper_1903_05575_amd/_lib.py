@@ -50,6 +50,8 @@ _SIGNATURES = {
                     _vp], _int),
     "qgemm_ex_s": ([_int, _int, _i64, _i64, _i64, _dp, _dp, _dp, _vp, _i64, _vp, _i64, _dp, _dp, _vp, _i64,
                     _int, _vp], _int),
+    "qherk_d": ([_int, _int, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _i64, _vp], _int),
+    "qherk_s": ([_int, _int, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _i64, _int, _vp], _int),
     "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
                                    _int, _int], _int),
     "qgemm_batched_run": ([_vp, _vp], _int),
@@ -285,5 +287,23 @@ def qgemm_ex(opA, opB, M, N, K, alpha_left, alpha_mid, alpha_right, A, lda, B, l
     elif dtype == torch.float32:
         rc = lib().qgemm_ex_s(*args, int(split_terms), _stream(stream))
         _raise(rc, "qgemm_ex_s")
+    else:
+        raise ValueError(f"unsupported dtype {dtype}")
+
+
+def qherk(uplo, trans, N, K, alpha, A, lda, beta, C, ldc, split_terms=6, stream=None):
+    """Hermitian rank-k update on the triangle uplo ('L' or 'U') of C:
+    alpha op(A) op(A)^H + beta C, op = trans ('N' or 'C'), alpha and beta real
+    (C-ABI qherk_d for float64 tensors, qherk_s for float32)."""
+    dtype = C.dtype
+    rows, cols = (N, K) if trans == "N" else (K, N)
+    if N and K:
+        _check_storage(A, rows, cols, lda, dtype, "A")
+    _check_storage(C, N, N, ldc, dtype, "C")
+    args = [{"L": 0, "U": 1}[uplo], OPS[trans], N, K, float(alpha), _ptr(A), lda, float(beta), _ptr(C), ldc]
+    if dtype == torch.float64:
+        _raise(lib().qherk_d(*args, _stream(stream)), "qherk_d")
+    elif dtype == torch.float32:
+        _raise(lib().qherk_s(*args, int(split_terms), _stream(stream)), "qherk_s")
     else:
         raise ValueError(f"unsupported dtype {dtype}")

@@ -84,6 +84,8 @@ qg::GemmDesc<T> make_desc(int opA, int opB, int64_t M, int64_t N, int64_t K, con
     d.store_t = false;
     d.store_conj = false;
     d.has_right = false;
+    d.uplo = 0;
+    d.herm_diag = false;
     for (int i = 0; i < 4; ++i) {
         d.alpha[i] = alpha[i];
         d.beta[i] = beta[i];
@@ -246,6 +248,53 @@ qgemm_status_t ex_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, const 
     return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
 }
 
+// Hermitian rank-k update on one triangle of C (BLAS HERK convention, alpha
+// and beta real): trans N: C <- alpha A A^H + beta C (A n x k); trans C:
+// C <- alpha A^H A + beta C (A k x n).  The GEMM kernels run with B = A and
+// the adjoint op; tiles outside the triangle exit at once and the epilogue
+// writes only the triangle, with a real diagonal.
+// Arguments: 1 uplo, 2 trans, 3 N, 4 K, 5 alpha, 6 A, 7 lda, 8 beta, 9 C,
+// 10 ldc, 11 split_terms (FP32 only).
+template <typename T>
+qgemm_status_t herk_impl(int uplo, int trans, int64_t N, int64_t K, double alpha, const T *A, int64_t lda,
+                         double beta, T *C, int64_t ldc, int split_terms, hipStream_t stream)
+{
+    constexpr uintptr_t align = 4 * sizeof(T);
+    g_bad_arg = 0;
+    if (uplo != QGEMM_LOWER && uplo != QGEMM_UPPER) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (trans != QGEMM_OP_N && trans != QGEMM_OP_C) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (N < 0) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (K < 0) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (N > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 3);
+    if (K > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 4);
+    const int64_t rows_a = trans == QGEMM_OP_N ? N : K;
+    if (lda < (rows_a > 1 ? rows_a : 1)) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    if (ldc < (N > 1 ? N : 1)) return fail(QGEMM_ERR_INVALID_ARG, 10);
+    if (sizeof(T) == 4) {
+        if (split_terms == 0) split_terms = 6;
+        if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 11);
+    }
+    if (N == 0) return QGEMM_OK;
+    if ((alpha == 0.0 || K == 0) && beta == 1.0) return QGEMM_OK;     // nothing to update
+    const bool reads_a = K > 0 && alpha != 0.0;
+    if (reads_a && !A) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (!C) return fail(QGEMM_ERR_INVALID_ARG, 9);
+    if (reads_a && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 6);
+    if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 9);
+    const bool ta = trans == QGEMM_OP_C;
+    const bool ld_ok = sizeof(T) == 4 ? qg::split_ld_supported(lda, lda, ta, !ta) : qg::f64_ld_supported(lda, lda, ta, !ta);
+    if (!ld_ok) return fail(QGEMM_ERR_UNSUPPORTED, 7);
+    const double al[4] = {alpha, 0.0, 0.0, 0.0};
+    const double be[4] = {beta, 0.0, 0.0, 0.0};
+    auto d = make_desc<T>(trans, adjoint_op(trans), N, N, K, al, A, lda, A, lda, be, C, ldc);
+    d.uplo = uplo == QGEMM_LOWER ? 1 : 2;
+    d.herm_diag = true;
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) e = qg::launch_qgemm_f64(d, stream);
+    else e = qg::launch_qgemm_bf16x3(d, nullptr, split_terms, qg::kSplitPanel, stream);
+    return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -326,6 +375,19 @@ qgemm_status_t qgemm_ex_s(int opA, int opB, int64_t M, int64_t N, int64_t K, con
 {
     return ex_impl<float>(opA, opB, M, N, K, alpha_left, alpha_mid, alpha_right, A, lda, B, ldb, beta_left,
                           beta_right, C, ldc, split_terms, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qherk_d(int uplo, int trans, int64_t N, int64_t K, double alpha, const double *A, int64_t lda,
+                       double beta, double *C, int64_t ldc, void *stream)
+{
+    return herk_impl<double>(uplo, trans, N, K, alpha, A, lda, beta, C, ldc, 6, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qherk_s(int uplo, int trans, int64_t N, int64_t K, double alpha, const float *A, int64_t lda,
+                       double beta, float *C, int64_t ldc, int split_terms, void *stream)
+{
+    return herk_impl<float>(uplo, trans, N, K, alpha, A, lda, beta, C, ldc, split_terms,
+                            static_cast<hipStream_t>(stream));
 }
 
 qgemm_status_t qgemm_backward_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,

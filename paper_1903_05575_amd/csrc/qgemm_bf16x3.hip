@@ -17,7 +17,8 @@ __global__ __launch_bounds__(split::NT, STAGES == 1 ? 2 : 1) void qgemm_bf16x3_k
 {
     extern __shared__ unsigned lds[];
     int tm, tn;
-    xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+    if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+    else xcd_tri_tile(blockIdx.x, gridDim.x, p.uplo == 1, tm, tn);   // triangular output: its tiles only
     if (p.has_bscale)
         split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, true>(p, c64, tm * TL::BM, tn * TL::BN, nk, panel_tiles, lds);
     else
@@ -41,7 +42,8 @@ hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, hipStream_
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
     const int nk = alpha_zero ? 0 : (d.K + TL::BK - 1) / TL::BK;
     const int panel_tiles = panel / TL::BK > 0 ? panel / TL::BK : 1;
-    const int64_t nblocks = (int64_t)tiles_m * tiles_n;
+    static_assert(TL::BM == TL::BN, "triangular launches need square tiles");
+    const int64_t nblocks = d.uplo == 0 ? (int64_t)tiles_m * tiles_n : (int64_t)tiles_m * (tiles_m + 1) / 2;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(split::NT), lds_bytes, stream, d, c64, tiles_m,

@@ -353,6 +353,7 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                 const int mu = m0 + a_row - (fi >> 2) + 8 * m + 2 * j + fg;
                 const int nu = n0 + b_row + 32 * n;
                 if (mu >= p.M || nu >= p.N) continue;
+                if (p.uplo != 0 && (p.uplo == 1 ? mu < nu : mu > nu)) continue;
                 const int64_t e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
                 if constexpr (C64) {
                     const double v[4] = {tot[m][n][4 * j], tot[m][n][4 * j + 1], tot[m][n][4 * j + 2],
@@ -375,6 +376,7 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                         }
                         o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                     }
+                    if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.0;
                     dst[0] = o[0]; dst[1] = o[1]; dst[2] = o[2]; dst[3] = o[3];
                 } else {
                     const float al[4] = {(float)p.alpha[0], (float)p.alpha[1], (float)p.alpha[2], (float)p.alpha[3]};
@@ -402,6 +404,7 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                         }
                         o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                     }
+                    if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.f;
                     *dst = (f32x4){o[0], o[1], o[2], o[3]};
                 }
             }

@@ -27,17 +27,23 @@ __device__ __forceinline__ void qmul(const T p[4], const T q[4], T out[4])
 
 // Blocks are dispatched round-robin over the 8 XCDs of the MI355X (block b
 // runs on XCD b % 8, each XCD with its own L2).  Renumber so that every XCD
-// owns one contiguous range of tile ids, then raster those ids in groups of
-// `group` tile rows so neighbouring tiles on one XCD share A and B panels.
-__device__ __forceinline__ void xcd_tile(int bid, int nblocks, int tiles_m, int tiles_n,
-                                         int group, int &tm, int &tn)
+// owns one contiguous range of work ids.
+__device__ __forceinline__ int xcd_id(int bid, int nblocks)
 {
     const int xcd = bid & 7;
     const int local = bid >> 3;
     const int per = nblocks >> 3;
     const int rem = nblocks & 7;
-    const int id = (xcd < rem) ? xcd * (per + 1) + local
-                               : rem * (per + 1) + (xcd - rem) * per + local;
+    return (xcd < rem) ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Tile of a tiles_m x tiles_n grid for block bid: XCD-contiguous ids rastered
+// in groups of `group` tile rows, so neighbouring tiles on one XCD share A and
+// B panels.
+__device__ __forceinline__ void xcd_tile(int bid, int nblocks, int tiles_m, int tiles_n,
+                                         int group, int &tm, int &tn)
+{
+    const int id = xcd_id(bid, nblocks);
     const int gsz = group * tiles_n;
     const int g = id / gsz;
     const int first_m = g * group;
@@ -45,6 +51,20 @@ __device__ __forceinline__ void xcd_tile(int bid, int nblocks, int tiles_m, int 
     const int within = id - g * gsz;
     tm = first_m + within % gm;
     tn = within / gm;
+}
+
+// Tile of the lower (tm >= tn) or upper (tm <= tn) triangle of a square tile
+// grid for block bid; the grid has exactly T (T + 1) / 2 blocks, enumerated
+// row by row of the lower triangle, so every XCD gets an equal share.
+__device__ __forceinline__ void xcd_tri_tile(int bid, int nblocks, bool lower, int &tm, int &tn)
+{
+    const int id = xcd_id(bid, nblocks);
+    int r = (int)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+    while ((int64_t)r * (r + 1) / 2 > id) --r;
+    while ((int64_t)(r + 1) * (r + 2) / 2 <= id) ++r;
+    const int c = id - r * (r + 1) / 2;
+    tm = lower ? r : c;
+    tn = lower ? c : r;
 }
 
 }  // namespace qg

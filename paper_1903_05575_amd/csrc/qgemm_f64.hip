@@ -76,7 +76,8 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     const int wave = tid >> 6;
 
     int tm, tn;
-    xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+    if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+    else xcd_tri_tile(blockIdx.x, gridDim.x, p.uplo == 1, tm, tn);   // triangular output: its tiles only
     const int m0 = tm * BM, n0 = tn * BN;
 
     // ---- per-lane constants of the A fragment (row i = lane % 16, column c = lane / 16)
@@ -227,7 +228,8 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int nu = n0 + 16 * n + (lane & 15);
-            if (mu < p.M && nu < p.N) {
+            const bool in_tri = p.uplo == 0 || (p.uplo == 1 ? mu >= nu : mu <= nu);
+            if (mu < p.M && nu < p.N && in_tri) {
                 const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
                 double o[4];
                 qmul(p.alpha, v, o);
@@ -249,6 +251,7 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
                     }
                     o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                 }
+                if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.0;
                 dst[0] = (d2){o[0], o[1]};
                 dst[1] = (d2){o[2], o[3]};
             }
@@ -270,7 +273,7 @@ hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
     const int tiles_n = (d.N + BN - 1) / BN;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
     const int nk = alpha_zero ? 0 : (d.K + BK - 1) / BK;
-    const int64_t nblocks = (int64_t)tiles_m * tiles_n;
+    const int64_t nblocks = d.uplo == 0 ? (int64_t)tiles_m * tiles_n : (int64_t)tiles_m * (tiles_m + 1) / 2;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB, BS>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,

@@ -85,6 +85,8 @@ __global__ __launch_bounds__(split::NT, kBlocksPerCU) void grouped_kernel(const 
         d.store_t = false;
         d.store_conj = false;
         d.has_right = false;
+        d.uplo = 0;
+        d.herm_diag = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             d.alpha[i] = s.alpha[i];

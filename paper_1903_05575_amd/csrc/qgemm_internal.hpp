@@ -31,6 +31,8 @@ struct GemmDesc {
     bool opA_t, conjA, opB_t, conjB;
     bool has_bscale, store_t, store_conj;
     bool has_right;        // alpha_r / beta_r are not both the unit quaternion
+    int uplo;              // 0: full C; 1: only mu >= nu (lower); 2: only mu <= nu (upper)
+    bool herm_diag;        // zero the vector part of diagonal results (Hermitian output)
     double alpha[4];
     double beta[4];
     double bscale[4];

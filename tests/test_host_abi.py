@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "qgemm.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(qgemm_\w+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(q[a-z]+_\w+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")
@@ -149,3 +149,17 @@ def test_validation_ex(L):
     # a zero middle scalar: A and B are not read, so NULL is accepted (N = 0: nothing launched)
     rc = L.qgemm_ex_d(0, 0, 4, 0, 4, n, q4(0, 0, 0, 0), n, None, 4, None, 4, n, n, FAKE, 4, n)
     assert rc == 0
+
+
+def test_validation_herk(L):
+    """qherk_* argument numbering: 1 uplo, 2 trans, 3 N, 4 K, 6 A, 7 lda, 9 C, 10 ldc, 11 split."""
+    d = ctypes.c_double
+    assert L.qherk_d(2, 0, 4, 4, d(1.0), FAKE, 4, d(0.0), FAKE, 4, None) == 1 and L.qgemm_last_invalid_arg() == 1
+    assert L.qherk_d(0, 1, 4, 4, d(1.0), FAKE, 4, d(0.0), FAKE, 4, None) == 1 and L.qgemm_last_invalid_arg() == 2
+    assert L.qherk_d(0, 0, 4, 4, d(1.0), FAKE, 3, d(0.0), FAKE, 4, None) == 1 and L.qgemm_last_invalid_arg() == 7
+    # trans C: A is K x N, lda >= K
+    assert L.qherk_d(0, 2, 8, 4, d(1.0), FAKE, 4, d(0.0), FAKE, 7, None) == 1 and L.qgemm_last_invalid_arg() == 10
+    assert L.qherk_d(1, 2, 8, 4, d(1.0), FAKE + 8, 4, d(0.0), FAKE, 8, None) == 2 and L.qgemm_last_invalid_arg() == 6
+    assert L.qherk_s(0, 0, 4, 4, d(1.0), FAKE, 4, d(0.0), FAKE, 4, 5, None) == 1 and L.qgemm_last_invalid_arg() == 11
+    # alpha == 0 with beta == 1: nothing to do, nothing is read
+    assert L.qherk_d(0, 0, 4, 4, d(0.0), None, 4, d(1.0), None, 4, None) == 0

@@ -399,6 +399,52 @@ def test_scalar_placement_reduces_to_left_form_and_differs():
     assert np.abs(left - mid).max() > 1e-2 and np.abs(mid - right).max() > 1e-2 and np.abs(left - right).max() > 1e-2
 
 
+# ---------------------------------------------------------------- Hermitian rank-k update
+@pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("trans", "NC")
+def test_qherk_vs_complex_embedding(uplo, trans):
+    """The triangle of alpha op(A) op(A)^H + beta C equals the quaternion read
+    back from A_C A_C^H (numpy complex128) on the block representation; the
+    other triangle is untouched; the diagonal is real (Hermitian, Sec. 2.2)."""
+    n, k = 9, 7
+    g = W.rng(60 + len(uplo + trans))
+    rows, cols = (n, k) if trans == "N" else (k, n)
+    A = W.qmatrix(g, rows, cols, ld=rows + 1)
+    C = W.qmatrix(g, n, n, ld=n + 2)
+    alpha, beta = 0.7, -1.3
+    got = oracle.qherk(uplo, trans, n, k, alpha, A, rows + 1, beta, C, n + 2)
+    Ac = qref.complex_rep_block(qref.apply_op(trans, A, n, k))
+    P = qref.from_complex_block(Ac @ Ac.conj().T, n, n)
+    want = alpha * P + beta * qref.logical(C, n, n)
+    gl, cl = qref.logical(got, n, n), qref.logical(C, n, n)
+    for mu in range(n):
+        for nu in range(n):
+            inside = mu >= nu if uplo == "L" else mu <= nu
+            if not inside:
+                np.testing.assert_array_equal(gl[mu, nu], cl[mu, nu])
+            elif mu == nu:
+                assert gl[mu, mu, 0] == pytest.approx(want[mu, mu, 0], abs=1e-12)
+                assert (gl[mu, mu, 1:] == 0).all()
+            else:
+                np.testing.assert_allclose(gl[mu, nu], want[mu, nu], atol=1e-12)
+    # padding rows of C untouched
+    assert np.isnan(got[:, n:]).all()
+
+
+def test_qherk_matches_hermitian_product():
+    """A A^H is Hermitian: the lower result equals the conjugate transpose of the
+    upper result, off the diagonal."""
+    n, k = 8, 5
+    g = W.rng(66)
+    A = W.qmatrix(g, n, k)
+    Z = np.zeros((n, n, 4))
+    lo = qref.logical(oracle.qherk("L", "N", n, k, 1.0, A, n, 0.0, Z, n), n, n)
+    up = qref.logical(oracle.qherk("U", "N", n, k, 1.0, A, n, 0.0, Z, n), n, n)
+    for mu in range(n):
+        for nu in range(mu):
+            np.testing.assert_allclose(lo[mu, nu], np.asarray(qref.bf_conj(up[nu, mu])), atol=1e-13)
+
+
 # ---------------------------------------------------------------- gradient
 def _loss(opA, opB, M, N, K, al, A, lda, B, ldb, G, be, C0):
     out = oracle.qgemm(opA, opB, M, N, K, al, A, lda, B, ldb, be, C0, M)
