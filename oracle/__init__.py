@@ -64,6 +64,9 @@ def lib():
         L.oracle_qherk.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, ctypes.c_double, dp, i64,
                                    ctypes.c_double, dp, i64]
         L.oracle_qherk.restype = ctypes.c_int
+        L.oracle_qtrmm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, i64, i64, dp,
+                                   dp, i64, dp, i64, dp, i64]
+        L.oracle_qtrmm.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_max_threads.argtypes = []
@@ -142,6 +145,22 @@ def qherk(uplo, trans, n, k, alpha, A, lda, beta, C, ldc):
                             float(beta), _ptr(out), ldc)
     if rc != 0:
         raise RuntimeError(f"oracle_qherk failed ({rc})")
+    return out
+
+
+def qtrmm(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc):
+    """Triangular multiply alpha op(T) B (side 'L') or alpha B op(T) (side
+    'R'), T the triangle uplo ('L'/'U') of A with unit diagonal when diag is
+    'U'.  C only supplies the shape (N, ldc, 4) and the padding of the
+    result, which is returned as a new array."""
+    A = _f64(A)
+    B = _f64(B)
+    out = _f64(C).copy()
+    rc = lib().oracle_qtrmm({"L": 0, "R": 1}[side], {"L": 0, "U": 1}[uplo], OPS[trans], {"N": 0, "U": 1}[diag],
+                            M, N, _ptr(_f64(alpha)), _ptr(A), lda, _ptr(B), ldb,
+                            _ptr(out), ldc)
+    if rc != 0:
+        raise RuntimeError(f"oracle_qtrmm failed ({rc})")
     return out
 
 

@@ -266,6 +266,62 @@ int oracle_qherk(int uplo, int trans, int64_t n, int64_t k, double alpha, const 
     return 0;
 }
 
+/* Triangular matrix multiply (the XTRMM-like operation the GEMM kernels
+ * serve, Sec. 3), a reading in the BLAS TRMM convention, written out of
+ * place:
+ *   side = 0 (left):  C <- alpha op(T) B,  T is M x M
+ *   side = 1 (right): C <- alpha B op(T),  T is N x N
+ * B and C are M x N; alpha multiplies from the left (as in Eq. general_gemm).
+ * T is the triangle uplo (0 lower: r >= c, 1 upper: r <= c) of the stored A;
+ * the other triangle of A is not read.  diag = 1 (unit): T's diagonal is the
+ * unit quaternion and A's diagonal is not read.  op in {N, T, C, R} as for
+ * oracle_qgemm.  C is not read; alpha == 0: C <- 0 and neither A nor B is
+ * read.  Steps: form T densely, form op(T), then the plain triple sum.
+ * C must not overlap A or B.  Returns 0, -1 (allocation) or -2 (bad code). */
+int oracle_qtrmm(int side, int uplo, int trans, int diag, int64_t M, int64_t N,
+                 const double *alpha, const double *A, int64_t lda,
+                 const double *B, int64_t ldb, double *C, int64_t ldc)
+{
+    if ((side != 0 && side != 1) || (uplo != 0 && uplo != 1) || trans < 0 || trans > 3 ||
+        (diag != 0 && diag != 1))
+        return -2;
+    if (M <= 0 || N <= 0) return 0;
+    const int alpha_zero = (alpha[0] == 0.0 && alpha[1] == 0.0 && alpha[2] == 0.0 && alpha[3] == 0.0);
+    if (alpha_zero) {
+        for (int64_t nu = 0; nu < N; ++nu)
+            memset(C + 4 * nu * ldc, 0, sizeof(double) * 4 * (size_t)M);
+        return 0;
+    }
+    const int64_t n = side == 0 ? M : N;
+    double *T = (double *)calloc(4 * (size_t)(n * n), sizeof(double));
+    if (!T) return -1;
+    for (int64_t c = 0; c < n; ++c)
+        for (int64_t r = 0; r < n; ++r) {
+            double *t = T + 4 * (r + c * n);
+            if (r == c && diag == 1) t[0] = 1.0;
+            else if (uplo == 0 ? r >= c : r <= c) memcpy(t, A + 4 * (r + c * lda), 4 * sizeof(double));
+        }
+    double *opt = materialise_op(trans, n, n, T, n);
+    free(T);
+    if (!opt) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t nu = 0; nu < N; ++nu) {
+        for (int64_t mu = 0; mu < M; ++mu) {
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            const int64_t K = side == 0 ? M : N;
+            for (int64_t ka = 0; ka < K; ++ka) {
+                double t[4];
+                if (side == 0) oracle_hamilton(opt + 4 * (mu + ka * n), B + 4 * (ka + nu * ldb), t);
+                else           oracle_hamilton(B + 4 * (mu + ka * ldb), opt + 4 * (ka + nu * n), t);
+                acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[3] += t[3];
+            }
+            oracle_hamilton(alpha, acc, C + 4 * (mu + nu * ldc));
+        }
+    }
+    free(opt);
+    return 0;
+}
+
 /* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *   C = alpha op(A) op(B) + beta C0.

@@ -445,6 +445,93 @@ def test_qherk_matches_hermitian_product():
             np.testing.assert_allclose(lo[mu, nu], np.asarray(qref.bf_conj(up[nu, mu])), atol=1e-13)
 
 
+# ---------------------------------------------------------------- triangular multiply
+def _tri_dense(p):
+    """Logical n x n triangle of p["A"] by numpy masking, unit diagonal
+    substituted: independent of the oracle's own construction."""
+    n = p["M"] if p["side"] == "L" else p["N"]
+    L = np.nan_to_num(qref.logical(p["A"], n, n))
+    mask = np.tril(np.ones((n, n))) if p["uplo"] == "L" else np.triu(np.ones((n, n)))
+    if p["diag"] == "U":
+        mask = mask - np.eye(n)
+    T = L * mask[:, :, None]
+    if p["diag"] == "U":
+        T[np.arange(n), np.arange(n), 0] = 1.0
+    return T, n
+
+
+def _trmm_via_complex(p):
+    """alpha op(T) B or alpha B op(T) via complex128 block products (Eq. hc_mat_mult)."""
+    T, n = _tri_dense(p)
+    M, N = p["M"], p["N"]
+    Ts = np.ascontiguousarray(T.transpose(1, 0, 2))          # storage layout of T, ld = n
+    Tc = qref.complex_rep_block(qref.apply_op(p["trans"], Ts, n, n))
+    Bc = qref.complex_rep_block(qref.logical(p["B"], M, N))
+    P = Tc @ Bc if p["side"] == "L" else Bc @ Tc
+    return qref.from_complex_block(qref.scalar_block(p["alpha"], M) @ P, M, N)
+
+
+def _oracle_trmm(p):
+    return oracle.qtrmm(p["side"], p["uplo"], p["trans"], p["diag"], p["M"], p["N"], p["alpha"], p["A"],
+                        p["lda"], p["B"], p["ldb"], p["C"], p["ldc"])
+
+
+@pytest.mark.parametrize("side", "LR")
+@pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("trans", "NTCR")
+@pytest.mark.parametrize("diag", "NU")
+def test_qtrmm_vs_complex_embedding(side, uplo, trans, diag):
+    """Triangular multiply against the complex block representation of the
+    dense triangle; the unreferenced triangle (and a unit diagonal) of A hold
+    NaN, so reading them would show; C's padding stays untouched."""
+    M, N = 7, 5
+    p = W.trmm_problem(70 + "LR".index(side) * 16 + "LU".index(uplo) * 8 + "NTCR".index(trans) * 2
+                       + "NU".index(diag), side, uplo, trans, diag, M, N, dist="normal", pad=1)
+    got = _oracle_trmm(p)
+    np.testing.assert_allclose(qref.logical(got, M, N), _trmm_via_complex(p), atol=1e-12)
+    assert np.isnan(got[:, M:]).all()
+
+
+def test_qtrmm_uplo_trans_duality():
+    """The lower triangle of A equals (upper triangle of A^T)^T, so
+    op N on lower A and op T on upper A^T (stored transposed) agree exactly."""
+    M, N = 6, 4
+    p = W.trmm_problem(90, "L", "L", "N", "N", M, N, dist="normal")
+    q = dict(p, uplo="U", trans="T", A=np.ascontiguousarray(p["A"].transpose(1, 0, 2)))
+    np.testing.assert_array_equal(_oracle_trmm(p), _oracle_trmm(q))
+
+
+def test_qtrmm_sides_related_by_adjoint():
+    """(B T)^H = T^H B^H: the right-side product with op N equals the conjugate
+    transpose of the left-side product with op C on B^H (alpha = 1)."""
+    M, N = 5, 6
+    p = W.trmm_problem(91, "R", "U", "N", "N", M, N, dist="normal", alpha=[1.0, 0, 0, 0])
+    right = qref.logical(_oracle_trmm(p), M, N)
+    BH = qref.apply_op("C", p["B"], N, M)                      # logical N x M
+    q = dict(p, side="L", trans="C", M=N, N=M, B=np.ascontiguousarray(BH.transpose(1, 0, 2)), ldb=N,
+             C=np.zeros((M, N, 4)), ldc=N)
+    left = qref.logical(_oracle_trmm(q), N, M)
+    np.testing.assert_allclose(right, qref.apply_op("C", np.ascontiguousarray(left.transpose(1, 0, 2)), M, N),
+                               atol=1e-12)
+
+
+def test_qtrmm_identity_and_alpha_zero():
+    """A unit triangle whose strict part is zero is the identity: C = alpha B
+    (to the rounding of one Hamilton product).  alpha = 0 gives zeros without reading A or B (both all NaN)."""
+    M, N = 5, 3
+    p = W.trmm_problem(92, "L", "U", "C", "U", M, N, dist="normal")
+    A = np.full_like(p["A"], np.nan)
+    for c in range(M):
+        A[c, :c] = 0.0                                         # strict upper part of column c
+    got = qref.logical(_oracle_trmm(dict(p, A=A)), M, N)
+    want = np.array([[qref.bf_mul(p["alpha"], qref.logical(p["B"], M, N)[i, j]) for j in range(N)]
+                     for i in range(M)])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-15)
+    nanB = np.full_like(p["B"], np.nan)
+    z = _oracle_trmm(dict(p, A=np.full_like(p["A"], np.nan), B=nanB, alpha=np.zeros(4)))
+    assert (qref.logical(z, M, N) == 0).all()
+
+
 # ---------------------------------------------------------------- gradient
 def _loss(opA, opB, M, N, K, al, A, lda, B, ldb, G, be, C0):
     out = oracle.qgemm(opA, opB, M, N, K, al, A, lda, B, ldb, be, C0, M)
@@ -517,6 +604,11 @@ MUTANTS = [
     ("else                    src = X + 4 * (c + r * ldx);", "else                    src = X + 4 * (r + c * ldx);"),  # T forgets transpose
     ("if (!beta_zero) oracle_hamilton(beta, c, u);", "if (!beta_zero) oracle_hamilton(c, beta, u);"),  # beta right
     ("for (int64_t ka = 0; ka < K; ++ka) {\n                const double *b", "for (int64_t ka = 1; ka < K; ++ka) {\n                const double *b"),  # dropped term
+    ("else if (uplo == 0 ? r >= c : r <= c)", "else if (uplo == 0 ? r > c : r <= c)"),   # trmm drops the diagonal
+    ("if (r == c && diag == 1) t[0] = 1.0;", "if (r == c && diag == 1) t[3] = 1.0;"),     # unit diagonal wrong
+    ("else           oracle_hamilton(B + 4 * (mu + ka * ldb), opt + 4 * (ka + nu * n), t);",
+     "else           oracle_hamilton(opt + 4 * (ka + nu * n), B + 4 * (mu + ka * ldb), t);"),  # right side commuted
+    ("oracle_hamilton(alpha, acc, C + 4 * (mu + nu * ldc));", "oracle_hamilton(acc, alpha, C + 4 * (mu + nu * ldc));"),  # trmm alpha right
 ]
 
 
@@ -558,6 +650,15 @@ def _mutant_pins_fail(so):
                                  qref.logical(p["C"], M, N))
             if not np.allclose(qref.logical(out, M, N), want, atol=1e-12):
                 return True
+    L.oracle_qtrmm.argtypes = [ctypes.c_int] * 4 + [i64, i64, dp, dp, i64, dp, i64, dp, i64]
+    for side, uplo, trans, diag in (("L", "L", "N", "N"), ("R", "U", "C", "U"), ("L", "U", "T", "U"),
+                                    ("R", "L", "N", "N")):
+        t = W.trmm_problem(8, side, uplo, trans, diag, 4, 5, dist="normal", pad=1)
+        out = np.ascontiguousarray(t["C"].copy())
+        L.oracle_qtrmm("LR".index(side), "LU".index(uplo), "NTCR".index(trans), "NU".index(diag), 4, 5,
+                       P(t["alpha"]), P(t["A"]), t["lda"], P(t["B"]), t["ldb"], P(out), t["ldc"])
+        if not np.allclose(qref.logical(out, 4, 5), _trmm_via_complex(t), atol=1e-12):
+            return True
     return False
 
 

@@ -85,6 +85,27 @@ def gemm_problem(seed, M, N, K, opA="N", opB="N", dist="uniform", dtype=np.float
                 B=B, ldb=ldb, C=C, ldc=ldc)
 
 
+def trmm_problem(seed, side, uplo, trans, diag, M, N, dist="uniform", dtype=np.float64, alpha=None, pad=0):
+    """Triangular multiply inputs: a stored n x n A (n = M for side 'L', N for
+    side 'R') whose triangle opposite to ``uplo`` holds NaN, as does its
+    diagonal when ``diag`` is 'U' (those entries must not be read), B and an
+    all-NaN C (written, never read), each leading dimension padded by ``pad``."""
+    g = rng(seed)
+    n = M if side == "L" else N
+    lda, ldb, ldc = max(n, 1) + pad, max(M, 1) + pad, max(M, 1) + pad
+    A = qmatrix(g, n, n, ld=lda, dist=dist, dtype=dtype)
+    r = np.arange(n)
+    unread = (r[None, :] < r[:, None]) if uplo == "L" else (r[None, :] > r[:, None])   # [col, row]
+    if diag == "U":
+        unread = unread | (r[None, :] == r[:, None])
+    A[:, :n, :][unread] = np.nan
+    B = qmatrix(g, M, N, ld=ldb, dist=dist, dtype=dtype)
+    C = np.full((max(N, 0), ldc, 4), np.nan, dtype=dtype)
+    al = quaternion(g) if alpha is None else np.asarray(alpha, dtype=np.float64)
+    return dict(side=side, uplo=uplo, trans=trans, diag=diag, M=M, N=N, alpha=al, A=A, lda=lda, B=B, ldb=ldb,
+                C=C, ldc=ldc)
+
+
 SWEEP_SIZES = (1024, 2048, 4096, 8192)
 OP_PAIRS = tuple((a, b) for a in "NTC" for b in "NTC")
 
