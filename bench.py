@@ -18,7 +18,7 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    rate and its error against the oracle on sampled outputs.
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
-    python bench.py --only fp64|split|grouped|linear|scalars|herk    one part, no CPU baseline
+    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm    one part, no CPU baseline
 """
 import argparse
 import hashlib
@@ -293,6 +293,29 @@ def variant_herk(steps, warmup):
                                      "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}}
 
 
+def variant_trmm(steps, warmup):
+    """Triangular multiply qtrmm_d: C <- alpha L B with L the lower triangle of
+    A (side left, op N, non-unit diagonal), M = N = 8192 FP64; the upper
+    triangle of A holds NaN (never read).  Effective flops 32 N M (M + 1) / 2;
+    error on 16 whole columns against the oracle's qtrmm."""
+    import oracle
+    n = 8192
+    t = W.trmm_problem(W.BASE_SEED + 8, "L", "L", "N", "N", n, n)
+    Ad, Bd = dev(t["A"]), dev(t["B"])
+    Cd = torch.empty_like(Bd)
+    al = t["alpha"]
+    _, ev = time_launches(lambda: q.qtrmm("L", "L", "N", "N", n, n, al, Ad, n, Bd, n, Cd, n), steps, warmup)
+    gs = np.random.default_rng(9)
+    cols = np.sort(gs.choice(n, 16, replace=False))
+    Bs = np.ascontiguousarray(t["B"][cols])
+    want = oracle.qtrmm("L", "L", "N", "N", n, 16, al, t["A"], n, Bs, n, np.zeros_like(Bs), n)
+    got = Cd.cpu().numpy()[cols]
+    fl = 32 * n * n * (n + 1) // 2
+    return {"fp64_trmm_8192_left_lower": {"ms": round(ev, 3), "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
+                                          "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4),
+                                          "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}}
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -313,7 +336,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -328,9 +351,9 @@ def main():
         calibrate_copy()
         return
 
-    if args.only in ("split", "grouped", "linear", "scalars", "herk"):
+    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm"):
         fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
-              "scalars": variant_scalars, "herk": variant_herk}[args.only]
+              "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm}[args.only]
         print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
@@ -380,7 +403,7 @@ def main():
     if not args.no_variants:
         variants = {}
         for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
-                         ("scalars", variant_scalars), ("herk", variant_herk)):
+                         ("scalars", variant_scalars), ("herk", variant_herk), ("trmm", variant_trmm)):
             log(f"[bench] variant {name}")
             variants.update(fn(args.steps, args.warmup))
             torch.cuda.empty_cache()

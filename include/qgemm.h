@@ -68,6 +68,16 @@ typedef enum {
 } qgemm_uplo_t;
 
 typedef enum {
+    QGEMM_SIDE_LEFT = 0,
+    QGEMM_SIDE_RIGHT = 1
+} qgemm_side_t;
+
+typedef enum {
+    QGEMM_NON_UNIT = 0,
+    QGEMM_UNIT = 1
+} qgemm_diag_t;
+
+typedef enum {
     QGEMM_OK = 0,
     QGEMM_ERR_INVALID_ARG = 1,
     QGEMM_ERR_MISALIGNED = 2,
@@ -177,6 +187,33 @@ qgemm_status_t qherk_d(int uplo, int trans, int64_t N, int64_t K, double alpha,
                        void *stream);
 qgemm_status_t qherk_s(int uplo, int trans, int64_t N, int64_t K, double alpha,
                        const float *A, int64_t lda, double beta, float *C, int64_t ldc,
+                       int split_terms, void *stream);
+
+/*
+ * qtrmm_d / qtrmm_s -- triangular matrix multiply (the other BLAS-3
+ * operation the paper's GEMM kernels are meant to serve, Sec. 3), in the BLAS
+ * TRMM convention but out of place:
+ *     side = QGEMM_SIDE_LEFT:   C <- alpha op(T) B,   T is M x M
+ *     side = QGEMM_SIDE_RIGHT:  C <- alpha B op(T),   T is N x N
+ * B and C are M x N (leading dimensions ldb, ldc >= max(1, M)); alpha is a
+ * quaternion multiplying from the left, as in qgemm_d.  T is the triangle
+ * `uplo` (QGEMM_LOWER: row >= column, QGEMM_UPPER: row <= column) of the
+ * stored A (lda >= max(1, order of T)); A's other triangle is never read.
+ * diag = QGEMM_UNIT: T's diagonal is the unit quaternion and A's diagonal is
+ * not read.  trans is any op (N, T, C or R) applied to T.  C is written, not
+ * read, and must not overlap A or B (checked: QGEMM_ERR_INVALID_ARG on C).
+ * alpha == 0: C <- 0 and A, B are not read.  Each output tile walks only the
+ * K-range the triangle covers, so the work is about half that of qgemm_d.
+ * Arguments: 1 side, 2 uplo, 3 trans, 4 diag, 5 M, 6 N, 7 alpha, 8 A,
+ *   9 lda, 10 B, 11 ldb, 12 C, 13 ldc, then (qtrmm_s only) 14 split_terms,
+ *   then stream.
+ */
+qgemm_status_t qtrmm_d(int side, int uplo, int trans, int diag, int64_t M, int64_t N,
+                       const double *alpha, const double *A, int64_t lda,
+                       const double *B, int64_t ldb, double *C, int64_t ldc, void *stream);
+qgemm_status_t qtrmm_s(int side, int uplo, int trans, int diag, int64_t M, int64_t N,
+                       const double *alpha, const float *A, int64_t lda,
+                       const float *B, int64_t ldb, float *C, int64_t ldc,
                        int split_terms, void *stream);
 
 /*

@@ -52,6 +52,8 @@ _SIGNATURES = {
                     _int, _vp], _int),
     "qherk_d": ([_int, _int, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _i64, _vp], _int),
     "qherk_s": ([_int, _int, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _i64, _int, _vp], _int),
+    "qtrmm_d": ([_int, _int, _int, _int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _int),
+    "qtrmm_s": ([_int, _int, _int, _int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp], _int),
     "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
                                    _int, _int], _int),
     "qgemm_batched_run": ([_vp, _vp], _int),
@@ -305,5 +307,27 @@ def qherk(uplo, trans, N, K, alpha, A, lda, beta, C, ldc, split_terms=6, stream=
         _raise(lib().qherk_d(*args, _stream(stream)), "qherk_d")
     elif dtype == torch.float32:
         _raise(lib().qherk_s(*args, int(split_terms), _stream(stream)), "qherk_s")
+    else:
+        raise ValueError(f"unsupported dtype {dtype}")
+
+
+def qtrmm(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc, split_terms=6, stream=None):
+    """Triangular multiply C <- alpha op(T) B (side 'L') or alpha B op(T)
+    (side 'R'), T the triangle uplo ('L'/'U') of A, unit diagonal when diag
+    is 'U' (C-ABI qtrmm_d for float64 tensors, qtrmm_s for float32).  C is
+    written only and must not overlap A or B."""
+    dtype = C.dtype
+    n = M if side == "L" else N
+    if M and N:
+        _check_storage(A, n, n, lda, dtype, "A")
+        _check_storage(B, M, N, ldb, dtype, "B")
+    _check_storage(C, M, N, ldc, dtype, "C")
+    pa, _ka = _q4(alpha)
+    args = [{"L": 0, "R": 1}[side], {"L": 0, "U": 1}[uplo], OPS[trans], {"N": 0, "U": 1}[diag], M, N, pa,
+            _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc]
+    if dtype == torch.float64:
+        _raise(lib().qtrmm_d(*args, _stream(stream)), "qtrmm_d")
+    elif dtype == torch.float32:
+        _raise(lib().qtrmm_s(*args, int(split_terms), _stream(stream)), "qtrmm_s")
     else:
         raise ValueError(f"unsupported dtype {dtype}")

@@ -86,6 +86,9 @@ qg::GemmDesc<T> make_desc(int opA, int opB, int64_t M, int64_t N, int64_t K, con
     d.has_right = false;
     d.uplo = 0;
     d.herm_diag = false;
+    d.tri = 0;
+    d.tri_lower = false;
+    d.tri_unit = false;
     for (int i = 0; i < 4; ++i) {
         d.alpha[i] = alpha[i];
         d.beta[i] = beta[i];
@@ -295,6 +298,73 @@ qgemm_status_t herk_impl(int uplo, int trans, int64_t N, int64_t K, double alpha
     return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
 }
 
+// Whether the bytes spanned by two column-major quaternion matrices (X: xrows x
+// xcols with leading dimension ldx, likewise Y) overlap.
+bool ranges_overlap(const void *X, int64_t ldx, int64_t xrows, int64_t xcols, const void *Y, int64_t ldy,
+                    int64_t yrows, int64_t ycols, int64_t qbytes)
+{
+    const uintptr_t x0 = reinterpret_cast<uintptr_t>(X), y0 = reinterpret_cast<uintptr_t>(Y);
+    const uintptr_t x1 = x0 + (uintptr_t)((ldx * (xcols - 1) + xrows) * qbytes);
+    const uintptr_t y1 = y0 + (uintptr_t)((ldy * (ycols - 1) + yrows) * qbytes);
+    return x0 < y1 && y0 < x1;
+}
+
+// Triangular multiply on the GEMM kernels: the triangular matrix is op(A)
+// (side left, K = M) or op(B) (side right, K = N) of one GEMM launch with
+// beta = 0.  Argument numbering as in include/qgemm.h.
+template <typename T>
+qgemm_status_t trmm_impl(int side, int uplo, int trans, int diag, int64_t M, int64_t N, const double *alpha,
+                         const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t ldc, int split_terms,
+                         hipStream_t stream)
+{
+    constexpr uintptr_t align = 4 * sizeof(T);
+    g_bad_arg = 0;
+    if (side != QGEMM_SIDE_LEFT && side != QGEMM_SIDE_RIGHT) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (uplo != QGEMM_LOWER && uplo != QGEMM_UPPER) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (!valid_op(trans)) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (diag != QGEMM_NON_UNIT && diag != QGEMM_UNIT) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (M < 0) return fail(QGEMM_ERR_INVALID_ARG, 5);
+    if (N < 0) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (M > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 5);
+    if (N > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 6);
+    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    const int64_t n = side == QGEMM_SIDE_LEFT ? M : N;
+    if (lda < (n > 1 ? n : 1)) return fail(QGEMM_ERR_INVALID_ARG, 9);
+    if (ldb < (M > 1 ? M : 1)) return fail(QGEMM_ERR_INVALID_ARG, 11);
+    if (ldc < (M > 1 ? M : 1)) return fail(QGEMM_ERR_INVALID_ARG, 13);
+    if (sizeof(T) == 4) {
+        if (split_terms == 0) split_terms = 6;
+        if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 14);
+    }
+    if (M == 0 || N == 0) return QGEMM_OK;
+    const bool reads_ab = !is_zero4(alpha);
+    if (reads_ab && !A) return fail(QGEMM_ERR_INVALID_ARG, 8);
+    if (reads_ab && !B) return fail(QGEMM_ERR_INVALID_ARG, 10);
+    if (!C) return fail(QGEMM_ERR_INVALID_ARG, 12);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 8);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(B) % align)) return fail(QGEMM_ERR_MISALIGNED, 10);
+    if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 12);
+    // C is written while A and B are still read by other tiles: no overlap
+    if (reads_ab && (ranges_overlap(C, ldc, M, N, A, lda, n, n, 4 * sizeof(T)) ||
+                     ranges_overlap(C, ldc, M, N, B, ldb, M, N, 4 * sizeof(T))))
+        return fail(QGEMM_ERR_INVALID_ARG, 12);
+    const bool left = side == QGEMM_SIDE_LEFT;
+    const bool ta = left ? op_transposes(trans) : false, tb = left ? false : op_transposes(trans);
+    const bool ld_ok = sizeof(T) == 4 ? qg::split_ld_supported(left ? lda : ldb, left ? ldb : lda, ta, tb)
+                                      : qg::f64_ld_supported(left ? lda : ldb, left ? ldb : lda, ta, tb);
+    if (!ld_ok) return fail(QGEMM_ERR_UNSUPPORTED, 9);
+    const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+    auto d = left ? make_desc<T>(trans, QGEMM_OP_N, M, N, M, alpha, A, lda, B, ldb, zero, C, ldc)
+                  : make_desc<T>(QGEMM_OP_N, trans, M, N, N, alpha, B, ldb, A, lda, zero, C, ldc);
+    d.tri = left ? 1 : 2;
+    d.tri_lower = (uplo == QGEMM_LOWER) != op_transposes(trans);   // the triangle after the op
+    d.tri_unit = diag == QGEMM_UNIT;
+    hipError_t e;
+    if constexpr (sizeof(T) == 8) e = qg::launch_qgemm_f64(d, stream);
+    else e = qg::launch_qgemm_bf16x3(d, nullptr, split_terms, qg::kSplitPanel, stream);
+    return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -387,6 +457,22 @@ qgemm_status_t qherk_s(int uplo, int trans, int64_t N, int64_t K, double alpha, 
                        double beta, float *C, int64_t ldc, int split_terms, void *stream)
 {
     return herk_impl<float>(uplo, trans, N, K, alpha, A, lda, beta, C, ldc, split_terms,
+                            static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qtrmm_d(int side, int uplo, int trans, int diag, int64_t M, int64_t N, const double *alpha,
+                       const double *A, int64_t lda, const double *B, int64_t ldb, double *C, int64_t ldc,
+                       void *stream)
+{
+    return trmm_impl<double>(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc, 6,
+                             static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qtrmm_s(int side, int uplo, int trans, int diag, int64_t M, int64_t N, const double *alpha,
+                       const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
+                       int split_terms, void *stream)
+{
+    return trmm_impl<float>(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc, split_terms,
                             static_cast<hipStream_t>(stream));
 }
 

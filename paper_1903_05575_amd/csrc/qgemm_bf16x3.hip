@@ -10,25 +10,33 @@ namespace {
 
 using TL = split::Tile<64, 64, 4, 1, 16>;
 
-template <bool TA, bool TB, int NTERMS, bool C64, int STAGES>
+template <bool TA, bool TB, int NTERMS, bool C64, int STAGES, int TRI>
 __global__ __launch_bounds__(split::NT, STAGES == 1 ? 2 : 1) void qgemm_bf16x3_kernel(GemmDesc<float> p, double *c64,
                                                                                    int tiles_m, int tiles_n, int nk,
                                                                                    int panel_tiles)
 {
     extern __shared__ unsigned lds[];
     int tm, tn;
-    if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
-    else xcd_tri_tile(blockIdx.x, gridDim.x, p.uplo == 1, tm, tn);   // triangular output: its tiles only
-    if (p.has_bscale)
-        split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, true>(p, c64, tm * TL::BM, tn * TL::BN, nk, panel_tiles, lds);
-    else
-        split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, false>(p, c64, tm * TL::BM, tn * TL::BN, nk, panel_tiles, lds);
+    if constexpr (TRI != 0) {   // triangular operand: work depends on the tile row (1) or column (2) only
+        xcd_chunk_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, TRI == 1, (TRI == 1) == p.tri_lower, tm, tn);
+        split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, false, TRI>(p, c64, tm * TL::BM, tn * TL::BN, nk,
+                                                                       panel_tiles, lds);
+    } else {
+        if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+        else xcd_tri_tile(blockIdx.x, gridDim.x, p.uplo == 1, tm, tn);   // triangular output: its tiles only
+        if (p.has_bscale)
+            split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, true>(p, c64, tm * TL::BM, tn * TL::BN, nk,
+                                                                     panel_tiles, lds);
+        else
+            split::split_tile<TL, TA, TB, NTERMS, C64, STAGES, false>(p, c64, tm * TL::BM, tn * TL::BN, nk,
+                                                                      panel_tiles, lds);
+    }
 }
 
-template <bool TA, bool TB, int NTERMS, bool C64, int STAGES>
+template <bool TA, bool TB, int NTERMS, bool C64, int STAGES, int TRI>
 hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
 {
-    auto kern = &qgemm_bf16x3_kernel<TA, TB, NTERMS, C64, STAGES>;
+    auto kern = &qgemm_bf16x3_kernel<TA, TB, NTERMS, C64, STAGES, TRI>;
     constexpr size_t lds_bytes = STAGES == 1 ? TL::LDS_BYTES_1 : TL::LDS_BYTES;
     static bool attr_set = false;
     if (!attr_set) {
@@ -53,19 +61,29 @@ hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, hipStream_
 
 // One LDS stage and two resident blocks per CU: measured faster than two
 // stages with one block (the second block's MFMAs cover this block's staging).
-template <bool TA, bool TB, int NTERMS, bool C64>
+template <bool TA, bool TB, int NTERMS, bool C64, int TRI>
 hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
 {
-    return launch_s<TA, TB, NTERMS, C64, 1>(d, c64, panel, stream);
+    return launch_s<TA, TB, NTERMS, C64, 1, TRI>(d, c64, panel, stream);
 }
 
-template <int NTERMS, bool C64>
+template <int NTERMS, bool C64, int TRI = 0>
 hipError_t dispatch_ops(const GemmDesc<float> &d, double *c64, int panel, hipStream_t s)
 {
-    if (d.opA_t) return d.opB_t ? launch_t<true, true, NTERMS, C64>(d, c64, panel, s)
-                                : launch_t<true, false, NTERMS, C64>(d, c64, panel, s);
-    return d.opB_t ? launch_t<false, true, NTERMS, C64>(d, c64, panel, s)
-                   : launch_t<false, false, NTERMS, C64>(d, c64, panel, s);
+    if (d.opA_t) return d.opB_t ? launch_t<true, true, NTERMS, C64, TRI>(d, c64, panel, s)
+                                : launch_t<true, false, NTERMS, C64, TRI>(d, c64, panel, s);
+    return d.opB_t ? launch_t<false, true, NTERMS, C64, TRI>(d, c64, panel, s)
+                   : launch_t<false, false, NTERMS, C64, TRI>(d, c64, panel, s);
+}
+
+template <int TRI>
+hipError_t dispatch_tri(const GemmDesc<float> &d, int nterms, int panel, hipStream_t s)
+{
+    switch (nterms) {
+    case 3: return dispatch_ops<3, false, TRI>(d, nullptr, panel, s);
+    case 9: return dispatch_ops<9, false, TRI>(d, nullptr, panel, s);
+    default: return dispatch_ops<6, false, TRI>(d, nullptr, panel, s);
+    }
 }
 
 }  // namespace
@@ -73,6 +91,11 @@ hipError_t dispatch_ops(const GemmDesc<float> &d, double *c64, int panel, hipStr
 hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream)
 {
     if (!split::split_offsets_fit(d.lda, d.ldb, d.opA_t, d.opB_t, TL::BM, TL::BN, TL::BK)) return hipErrorInvalidValue;
+    if (d.tri != 0) {
+        // a triangular operand is square and comes without a scale, a triangular output or an FP64 result
+        if (c64 || d.has_bscale || d.uplo != 0 || (d.tri == 1 ? d.K != d.M : d.K != d.N)) return hipErrorInvalidValue;
+        return d.tri == 1 ? dispatch_tri<1>(d, nterms, panel, stream) : dispatch_tri<2>(d, nterms, panel, stream);
+    }
     if (c64) {
         switch (nterms) {
         case 3: return dispatch_ops<3, true>(d, c64, panel, stream);

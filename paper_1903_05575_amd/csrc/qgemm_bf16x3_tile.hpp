@@ -156,9 +156,13 @@ struct Tile {
 // Loads are buffer loads from a per-K-tile resource: a masked element gets
 // the offset kOob, which the hardware reads as zero, so the K-loop has no
 // branches.  In-tile byte offsets are below 2^31 (see split_offsets_fit).
+// TRI = 1 (2): op(A) (op(B)) is the triangle of a triangular multiply: the
+// tile walks only the K-tiles the triangle reaches, elements across the
+// diagonal read as zero and a unit diagonal is staged in place of the
+// (unread) element.
 constexpr unsigned kOob = 0x80000000u;
 
-template <class TL, bool TA, bool TB, int NTERMS, bool C64, int STAGES, bool BS = false>
+template <class TL, bool TA, bool TB, int NTERMS, bool C64, int STAGES, bool BS = false, int TRI = 0>
 __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64, int m0, int n0, int nk,
                                            int panel_tiles, unsigned *lds)
 {
@@ -214,6 +218,17 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
     }
 
     u32x4 ra[TL::A_Q], rb[TL::B_Q];
+    unsigned unit_bits = 0;   // slots of the loaded tile on a unit diagonal (triangular operand)
+
+    // K-tiles this tile needs: all, or those a triangular operand reaches
+    int kt0 = 0, kt1 = nk;
+    if constexpr (TRI == 1) {
+        if (p.tri_lower) kt1 = min(nk, (m0 + BM + BK - 1) / BK);   // op(A)[mu][k] = 0 for k > mu
+        else kt0 = min(nk, m0 / BK);                                // op(A)[mu][k] = 0 for k < mu
+    } else if constexpr (TRI == 2) {
+        if (p.tri_lower) kt0 = min(nk, n0 / BK);                    // op(B)[k][nu] = 0 for k < nu
+        else kt1 = min(nk, (n0 + BN + BK - 1) / BK);                // op(B)[k][nu] = 0 for k > nu
+    }
 
     // fetch K-tile kt into registers (tiles at or past K read as zeros)
     auto load_tile = [&](int kt) {
@@ -223,12 +238,27 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
         const float *Bb = p.B + 4 * (TB ? ((int64_t)k0 * p.ldb + n0) : ((int64_t)n0 * p.ldb + k0));
         const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, 0x7fffffff, 0x00020000);
         const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, 0x7fffffff, 0x00020000);
+        if constexpr (TRI != 0) unit_bits = 0;
 #pragma unroll
-        for (int i = 0; i < TL::A_Q; ++i)
-            ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA, a_k[i] < krem ? a_off[i] : kOob, 0, 0);
+        for (int i = 0; i < TL::A_Q; ++i) {
+            bool ok = a_k[i] < krem;
+            if constexpr (TRI == 1) {
+                const int gm = m0 + a_r[i], gk = k0 + a_k[i];
+                ok = ok && (p.tri_lower ? gk <= gm : gk >= gm) && !(p.tri_unit && gk == gm);
+                if (p.tri_unit && gk == gm && gm < p.M) unit_bits |= 1u << i;
+            }
+            ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA, ok ? a_off[i] : kOob, 0, 0);
+        }
 #pragma unroll
-        for (int i = 0; i < TL::B_Q; ++i)
-            rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rB, b_k[i] < krem ? b_off[i] : kOob, 0, 0);
+        for (int i = 0; i < TL::B_Q; ++i) {
+            bool ok = b_k[i] < krem;
+            if constexpr (TRI == 2) {
+                const int gn = n0 + b_c[i], gk = k0 + b_k[i];
+                ok = ok && (p.tri_lower ? gk >= gn : gk <= gn) && !(p.tri_unit && gk == gn);
+                if (p.tri_unit && gk == gn && gn < p.N) unit_bits |= 1u << i;
+            }
+            rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? b_off[i] : kOob, 0, 0);
+        }
     };
 
     auto put = [&](unsigned *plane0, int plane_words, int row, int ka, float x, float y, float z, float w) {
@@ -244,13 +274,22 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
     auto store_tile = [&](unsigned *As) {
         unsigned *Bs = As + TL::A_STAGE;
 #pragma unroll
-        for (int i = 0; i < TL::A_Q; ++i)   // conj(A) is applied through L
-            put(As, BM * RP, a_r[i], a_k[i], __uint_as_float(ra[i].x), __uint_as_float(ra[i].y),
-                __uint_as_float(ra[i].z), __uint_as_float(ra[i].w));
+        for (int i = 0; i < TL::A_Q; ++i) {   // conj(A) is applied through L
+            u32x4 v = ra[i];
+            if constexpr (TRI == 1) {
+                if ((unit_bits >> i) & 1u) v = (u32x4){0x3f800000u, 0u, 0u, 0u};   // unit diagonal
+            }
+            put(As, BM * RP, a_r[i], a_k[i], __uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                __uint_as_float(v.w));
+        }
 #pragma unroll
         for (int i = 0; i < TL::B_Q; ++i) {
-            float b[4] = {__uint_as_float(rb[i].x), __uint_as_float(rb[i].y ^ conjB),
-                          __uint_as_float(rb[i].z ^ conjB), __uint_as_float(rb[i].w ^ conjB)};
+            u32x4 v = rb[i];
+            if constexpr (TRI == 2) {
+                if ((unit_bits >> i) & 1u) v = (u32x4){0x3f800000u, 0u, 0u, 0u};   // unit diagonal
+            }
+            float b[4] = {__uint_as_float(v.x), __uint_as_float(v.y ^ conjB),
+                          __uint_as_float(v.z ^ conjB), __uint_as_float(v.w ^ conjB)};
             if constexpr (BS) {
                 const float sc[4] = {(float)p.bscale[0], (float)p.bscale[1], (float)p.bscale[2], (float)p.bscale[3]};
                 float t[4];
@@ -304,39 +343,39 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
     unsigned *S0 = lds;
     if constexpr (STAGES == 2) {
         unsigned *S1 = lds + TL::STAGE;
-        if (nk > 0) {
-            load_tile(0);
+        if (kt0 < kt1) {
+            load_tile(kt0);
             store_tile(S0);
             __syncthreads();
         }
         // unrolled by two so that both stages are compile-time constants
-        int kt = 0;
-        while (kt < nk) {
+        int kt = kt0;
+        while (kt < kt1) {
             load_tile(kt + 1);
             compute(S0);
             store_tile(S1);
             __syncthreads();
             ++kt;
-            if (kt % panel_tiles == 0) flush();
-            if (kt >= nk) break;
+            if ((kt - kt0) % panel_tiles == 0) flush();
+            if (kt >= kt1) break;
             load_tile(kt + 1);
             compute(S1);
             store_tile(S0);
             __syncthreads();
             ++kt;
-            if (kt % panel_tiles == 0) flush();
+            if ((kt - kt0) % panel_tiles == 0) flush();
         }
     } else {
         // one stage: the next K-tile's loads are issued before this tile's
         // MFMAs so their latency hides behind the compute
-        if (nk > 0) load_tile(0);
-        for (int kt = 0; kt < nk; ++kt) {
-            if (kt > 0) __syncthreads();                 // every wave is done reading the stage
+        if (kt0 < kt1) load_tile(kt0);
+        for (int kt = kt0; kt < kt1; ++kt) {
+            if (kt > kt0) __syncthreads();               // every wave is done reading the stage
             store_tile(S0);
             __syncthreads();
             load_tile(kt + 1);
             compute(S0);
-            if ((kt + 1) % panel_tiles == 0) flush();
+            if ((kt + 1 - kt0) % panel_tiles == 0) flush();
         }
         __syncthreads();                                 // LDS may be reused by the caller
     }

@@ -67,4 +67,32 @@ __device__ __forceinline__ void xcd_tri_tile(int bid, int nblocks, bool lower, i
     tn = lower ? c : r;
 }
 
+// Tile for block bid when the work of a tile depends only on its tile row
+// (by_rows) or only on its tile column, as in a triangular multiply.  Tiles
+// are listed heaviest first (reverse: the heaviest row or column is the last
+// one) in groups of 8 rows (columns), each group rastered across the other
+// axis, so 64 consecutive list entries form an 8 x 8 patch.  In every full run
+// of 512 blocks (64 per XCD) XCD x takes the x-th patch of the run: the XCDs
+// always work on neighbouring patches of nearly equal weight, each patch
+// sharing its operand panels in one L2.  The last partial run is taken in
+// list order.  The map is a bijection from [0, tiles_m * tiles_n).
+__device__ __forceinline__ void xcd_chunk_tile(int bid, int nblocks, int tiles_m, int tiles_n, bool by_rows,
+                                               bool reverse, int &tm, int &tn)
+{
+    int pos = bid;
+    if (bid < (nblocks & ~511)) pos = (bid & ~511) + 64 * (bid & 7) + ((bid & 511) >> 3);
+    const int nw = by_rows ? tiles_m : tiles_n;
+    const int no = by_rows ? tiles_n : tiles_m;
+    const int gsz = 8 * no;
+    const int g = pos / gsz;
+    const int first = g * 8;
+    const int gw = min(nw - first, 8);
+    const int within = pos - g * gsz;
+    int w = first + within % gw;
+    const int o = within / gw;
+    if (reverse) w = nw - 1 - w;
+    tm = by_rows ? w : o;
+    tn = by_rows ? o : w;
+}
+
 }  // namespace qg

@@ -38,6 +38,12 @@
 //   B stage: [kappa][component][nu], plane pitch BN + 1; a fragment read is
 //            16 consecutive doubles per component.  op(B) conjugation and the
 //            optional left scale s are applied while writing this stage.
+// Triangular operand (TRI = 1: op(A), TRI = 2: op(B); triangular multiply):
+//   a tile walks only the K-tiles the triangle reaches from its rows
+//   (columns); elements across the diagonal take the zero-reading offset and
+//   a unit diagonal is written into LDS in place of the (unread) element, so
+//   the other triangle is never read.  Tiles are then ordered by weight, see
+//   xcd_chunk_tile.
 #include "qgemm_internal.hpp"
 
 namespace qg {
@@ -67,7 +73,7 @@ __device__ __forceinline__ double flip(double v, unsigned long long sign)
 
 constexpr unsigned kOob = 0x80000000u;   // buffer offset read as zero (masked element)
 
-template <bool TA, bool TB, bool BS>
+template <bool TA, bool TB, bool BS, int TRI>
 __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n, int nk)
 {
     extern __shared__ double smem[];
@@ -76,9 +82,21 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     const int wave = tid >> 6;
 
     int tm, tn;
-    if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
+    if constexpr (TRI != 0)   // work depends on the tile row (TRI 1) or column (TRI 2) only
+        xcd_chunk_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, TRI == 1, (TRI == 1) == p.tri_lower, tm, tn);
+    else if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
     else xcd_tri_tile(blockIdx.x, gridDim.x, p.uplo == 1, tm, tn);   // triangular output: its tiles only
     const int m0 = tm * BM, n0 = tn * BN;
+
+    // K-tiles this tile needs: all, or those a triangular operand reaches
+    int kt0 = 0, kt1 = nk;
+    if constexpr (TRI == 1) {
+        if (p.tri_lower) kt1 = min(nk, (m0 + BM + BK - 1) / BK);   // op(A)[mu][k] = 0 for k > mu
+        else kt0 = min(nk, m0 / BK);                                // op(A)[mu][k] = 0 for k < mu
+    } else if constexpr (TRI == 2) {
+        if (p.tri_lower) kt0 = min(nk, n0 / BK);                    // op(B)[k][nu] = 0 for k < nu
+        else kt1 = min(nk, (n0 + BN + BK - 1) / BK);                // op(B)[k][nu] = 0 for k > nu
+    }
 
     // ---- per-lane constants of the A fragment (row i = lane % 16, column c = lane / 16)
     const int fi = lane & 15;
@@ -100,6 +118,7 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
 
     d2 ra[A_CHUNKS];
     d2 rb[B_QUATS][2];
+    unsigned unit_bits = 0;   // slots of the loaded tile on a unit diagonal (triangular operand)
 
     // Staging coordinates of slot i (recomputed from the thread id where used,
     // which is cheaper than keeping them live in registers): A chunk i holds
@@ -131,17 +150,33 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
             int mu, ka, half;
             a_slot(i, mu, ka, half);
             const unsigned e = TA ? (unsigned)mu * (unsigned)p.lda + ka : (unsigned)ka * (unsigned)p.lda + mu;
-            const unsigned o = (m0 + mu < p.M && ka < krem) ? 32u * e + 16u * half : kOob;
-            ra[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rA, o, 0, 0));
+            bool ok = m0 + mu < p.M && ka < krem;
+            if constexpr (TRI == 1) {
+                const int gm = m0 + mu, gk = k0 + ka;
+                ok = ok && (p.tri_lower ? gk <= gm : gk >= gm) && !(p.tri_unit && gk == gm);
+            }
+            ra[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rA, ok ? 32u * e + 16u * half : kOob, 0, 0));
+            if constexpr (TRI == 1) {
+                if (i == 0) unit_bits = 0;
+                if (p.tri_unit && m0 + mu == k0 + ka && m0 + mu < p.M) unit_bits |= 1u << i;
+            }
         }
 #pragma unroll
         for (int i = 0; i < B_QUATS; ++i) {
             int nu, ka;
             b_slot(i, nu, ka);
             const unsigned e = TB ? (unsigned)ka * (unsigned)p.ldb + nu : (unsigned)nu * (unsigned)p.ldb + ka;
-            const bool ok = n0 + nu < p.N && ka < krem;
+            bool ok = n0 + nu < p.N && ka < krem;
+            if constexpr (TRI == 2) {
+                const int gn = n0 + nu, gk = k0 + ka;
+                ok = ok && (p.tri_lower ? gk >= gn : gk <= gn) && !(p.tri_unit && gk == gn);
+            }
             rb[i][0] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? 32u * e : kOob, 0, 0));
             rb[i][1] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? 32u * e + 16u : kOob, 0, 0));
+            if constexpr (TRI == 2) {
+                if (i == 0) unit_bits = 0;
+                if (p.tri_unit && n0 + nu == k0 + ka && n0 + nu < p.N) unit_bits |= 1u << i;
+            }
         }
     };
 
@@ -151,13 +186,20 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
         for (int i = 0; i < A_CHUNKS; ++i) {
             int mu, ka, half;
             a_slot(i, mu, ka, half);
-            *reinterpret_cast<d2 *>(As + ka * A_LD + mu * 4 + 2 * half) = ra[i];
+            d2 v = ra[i];
+            if constexpr (TRI == 1) {
+                if ((unit_bits >> i) & 1u) v = (d2){half ? 0.0 : 1.0, 0.0};   // unit diagonal, not read
+            }
+            *reinterpret_cast<d2 *>(As + ka * A_LD + mu * 4 + 2 * half) = v;
         }
 #pragma unroll
         for (int i = 0; i < B_QUATS; ++i) {
             int nu, ka;
             b_slot(i, nu, ka);
             double b[4] = {rb[i][0].x, rb[i][0].y, rb[i][1].x, rb[i][1].y};
+            if constexpr (TRI == 2) {
+                if ((unit_bits >> i) & 1u) { b[0] = 1.0; b[1] = b[2] = b[3] = 0.0; }   // unit diagonal, not read
+            }
 #pragma unroll
             for (int c = 1; c < 4; ++c)
                 b[c] = __longlong_as_double(__double_as_longlong(b[c]) ^ ((long long)conjB << 32));
@@ -207,14 +249,14 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
         }
     };
 
-    if (nk > 0) {
-        load_tile(0);
+    if (kt0 < kt1) {
+        load_tile(kt0);
         store_tile(smem);
         __syncthreads();
     }
-    // tiles past the end load as zeros and land in the unused stage
-    for (int kt = 0; kt < nk; ++kt) {
-        const int st = kt & 1;
+    // the tile after the last is loaded too and lands in the unused stage
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int st = (kt - kt0) & 1;
         load_tile(kt + 1);
         step_tile(smem + st * STAGE, smem + (st ^ 1) * STAGE);
         __syncthreads();
@@ -259,12 +301,12 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     }
 }
 
-template <bool TA, bool TB, bool BS>
+template <bool TA, bool TB, bool BS, int TRI>
 hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB, BS>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB, BS, TRI>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES);
         if (e != hipSuccess) return e;
         attr_set = true;
@@ -276,24 +318,29 @@ hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
     const int64_t nblocks = d.uplo == 0 ? (int64_t)tiles_m * tiles_n : (int64_t)tiles_m * (tiles_m + 1) / 2;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB, BS>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,
+    hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB, BS, TRI>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,
                        d, tiles_m, tiles_n, nk);
     return hipGetLastError();
 }
 
 }  // namespace
 
-template <bool BS>
+template <bool BS, int TRI>
 hipError_t launch_ops(const GemmDesc<double> &d, hipStream_t stream)
 {
-    if (d.opA_t) return d.opB_t ? launch_t<true, true, BS>(d, stream) : launch_t<true, false, BS>(d, stream);
-    return d.opB_t ? launch_t<false, true, BS>(d, stream) : launch_t<false, false, BS>(d, stream);
+    if (d.opA_t) return d.opB_t ? launch_t<true, true, BS, TRI>(d, stream) : launch_t<true, false, BS, TRI>(d, stream);
+    return d.opB_t ? launch_t<false, true, BS, TRI>(d, stream) : launch_t<false, false, BS, TRI>(d, stream);
 }
 
 hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream)
 {
     if (!f64_ld_supported(d.lda, d.ldb, d.opA_t, d.opB_t)) return hipErrorInvalidValue;
-    return d.has_bscale ? launch_ops<true>(d, stream) : launch_ops<false>(d, stream);
+    if (d.tri != 0) {
+        // a triangular operand is square and comes without a scale or a triangular output
+        if (d.has_bscale || d.uplo != 0 || (d.tri == 1 ? d.K != d.M : d.K != d.N)) return hipErrorInvalidValue;
+        return d.tri == 1 ? launch_ops<false, 1>(d, stream) : launch_ops<false, 2>(d, stream);
+    }
+    return d.has_bscale ? launch_ops<true, 0>(d, stream) : launch_ops<false, 0>(d, stream);
 }
 
 }  // namespace qg

@@ -33,6 +33,9 @@ struct GemmDesc {
     bool has_right;        // alpha_r / beta_r are not both the unit quaternion
     int uplo;              // 0: full C; 1: only mu >= nu (lower); 2: only mu <= nu (upper)
     bool herm_diag;        // zero the vector part of diagonal results (Hermitian output)
+    int tri;               // 0: none; 1: op(A) is triangular (K == M); 2: op(B) is triangular (K == N)
+    bool tri_lower;        // that triangular operand is zero above its diagonal (after the op)
+    bool tri_unit;         // its diagonal is the unit quaternion and is not read
     double alpha[4];
     double beta[4];
     double bscale[4];

@@ -163,3 +163,37 @@ def test_validation_herk(L):
     assert L.qherk_s(0, 0, 4, 4, d(1.0), FAKE, 4, d(0.0), FAKE, 4, 5, None) == 1 and L.qgemm_last_invalid_arg() == 11
     # alpha == 0 with beta == 1: nothing to do, nothing is read
     assert L.qherk_d(0, 0, 4, 4, d(0.0), None, 4, d(1.0), None, 4, None) == 0
+
+
+FAKE_B, FAKE_C = 0x20000, 0x30000    # disjoint from FAKE for 4 x 4 operands
+
+
+def call_trmm(L, side=0, uplo=0, trans=0, diag=0, M=4, N=4, alpha=ONE, A=FAKE, lda=4, B=FAKE_B, ldb=4,
+              C=FAKE_C, ldc=4):
+    return L.qtrmm_d(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc, None)
+
+
+@pytest.mark.parametrize("kw,arg,status", [
+    (dict(side=2), 1, 1), (dict(uplo=-1), 2, 1), (dict(trans=4), 3, 1), (dict(diag=2), 4, 1),
+    (dict(M=-1), 5, 1), (dict(N=-1), 6, 1), (dict(M=1 << 31), 5, 5), (dict(alpha=None), 7, 1),
+    (dict(lda=3), 9, 1), (dict(side=1, N=8, ldc=4, lda=4), 9, 1), (dict(ldb=3), 11, 1), (dict(ldc=3), 13, 1),
+    (dict(A=None), 8, 1), (dict(B=None), 10, 1), (dict(C=None), 12, 1),
+    (dict(A=FAKE + 8), 8, 2), (dict(B=FAKE_B + 16), 10, 2), (dict(C=FAKE_C + 24), 12, 2),
+    (dict(C=FAKE_B), 12, 1), (dict(C=FAKE + 256), 12, 1), (dict(B=FAKE_C + 480), 12, 1),
+])
+def test_validation_trmm(L, kw, arg, status):
+    """qtrmm_* argument numbering: 1 side, 2 uplo, 3 trans, 4 diag, 5 M, 6 N,
+    7 alpha, 8 A, 9 lda (>= order of the triangle), 10 B, 11 ldb, 12 C
+    (also: C overlapping A or B), 13 ldc, 14 split_terms."""
+    assert call_trmm(L, **kw) == status
+    assert L.qgemm_last_invalid_arg() == arg
+
+
+def test_validation_trmm_s_and_quick_return(L):
+    assert L.qtrmm_s(0, 0, 0, 0, 4, 4, ONE, FAKE, 4, FAKE_B, 4, FAKE_C, 4, 5, None) == 1
+    assert L.qgemm_last_invalid_arg() == 14
+    assert L.qtrmm_s(0, 0, 0, 0, 4, 4, ONE, FAKE + 8, 4, FAKE_B, 4, FAKE_C, 4, 6, None) == 2
+    assert L.qgemm_last_invalid_arg() == 8
+    # empty output: nothing read or written
+    assert call_trmm(L, M=0, A=None, B=None, C=None) == 0
+    assert call_trmm(L, N=0, A=None, B=None, C=None) == 0
