@@ -67,6 +67,8 @@ def lib():
         L.oracle_qtrmm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, i64, i64, dp,
                                    dp, i64, dp, i64, dp, i64]
         L.oracle_qtrmm.restype = ctypes.c_int
+        L.oracle_qgemm_mixed.argtypes = [ctypes.c_int] * 4 + [i64, i64, i64, dp, dp, i64, dp, i64, dp, dp, i64]
+        L.oracle_qgemm_mixed.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_max_threads.argtypes = []
@@ -161,6 +163,22 @@ def qtrmm(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc):
                             _ptr(out), ldc)
     if rc != 0:
         raise RuntimeError(f"oracle_qtrmm failed ({rc})")
+    return out
+
+
+TYPES = {"R": 1, "Z": 2, "Q": 4}
+
+
+def qgemm_mixed(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc):
+    """Mixed-type GEMM: typeA/typeB in 'R' (real, shape (cols, ld)), 'Z'
+    (complex, (cols, ld, 2)), 'Q' (quaternion, (cols, ld, 4)); the result is
+    a new quaternion (N, ldc, 4) array."""
+    A, B = _f64(A), _f64(B)
+    out = _f64(C).copy()
+    rc = lib().oracle_qgemm_mixed(TYPES[typeA], TYPES[typeB], OPS[opA], OPS[opB], M, N, K, _ptr(_f64(alpha)),
+                                  _ptr(A), lda, _ptr(B), ldb, _ptr(_f64(beta)), _ptr(out), ldc)
+    if rc != 0:
+        raise RuntimeError(f"oracle_qgemm_mixed failed ({rc})")
     return out
 
 

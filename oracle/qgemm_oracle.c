@@ -322,6 +322,46 @@ int oracle_qtrmm(int side, int uplo, int trans, int diag, int64_t M, int64_t N,
     return 0;
 }
 
+/* Mixed-type GEMM (the quaternion-real and quaternion-complex arithmetic of
+ * Sec. 5): one operand is a real or complex matrix, embedded into the
+ * quaternions by x -> x e0 and z = z0 + z1 i -> z0 e0 + z1 e1 (the complex
+ * subalgebra of Eq. complex_subalg and the map Eq. h_c_iso); then
+ * C <- alpha op(A) op(B) + beta C exactly as oracle_qgemm.  typeA, typeB
+ * give the reals per stored element: 1 real, 2 complex (re, im
+ * interleaved), 4 quaternion; leading dimensions count elements.  op T
+ * transposes, C conjugate-transposes (complex conjugate = quaternion
+ * conjugate of the embedding), R conjugates.  Returns 0, -1 (allocation) or
+ * -2 (bad code). */
+static double *embed(int type, int op, int64_t rows, int64_t cols, const double *X, int64_t ldx)
+{
+    /* stored dimensions of X for this op */
+    const int64_t sr = (op == 0 || op == 3) ? rows : cols, sc = (op == 0 || op == 3) ? cols : rows;
+    double *Q = (double *)calloc(4 * (size_t)(sr * sc > 0 ? sr * sc : 1), sizeof(double));
+    if (!Q) return NULL;
+    for (int64_t c = 0; c < sc; ++c)
+        for (int64_t r = 0; r < sr; ++r)
+            for (int k = 0; k < type; ++k)
+                Q[4 * (r + c * sr) + k] = X[type * (r + c * ldx) + k];
+    return Q;
+}
+
+int oracle_qgemm_mixed(int typeA, int typeB, int opA, int opB, int64_t M, int64_t N, int64_t K,
+                       const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                       const double *beta, double *C, int64_t ldc)
+{
+    const int okA = typeA == 1 || typeA == 2 || typeA == 4, okB = typeB == 1 || typeB == 2 || typeB == 4;
+    if (!okA || !okB || opA < 0 || opA > 3 || opB < 0 || opB > 3) return -2;
+    if (M <= 0 || N <= 0) return 0;
+    double *Aq = embed(typeA, opA, M, K, A, lda);
+    double *Bq = embed(typeB, opB, K, N, B, ldb);
+    if (!Aq || !Bq) { free(Aq); free(Bq); return -1; }
+    const int64_t la = (opA == 0 || opA == 3) ? M : K, lb = (opB == 0 || opB == 3) ? K : N;
+    const int rc = oracle_qgemm(opA, opB, M, N, K, alpha, Aq, la > 0 ? la : 1, Bq, lb > 0 ? lb : 1, beta, C, ldc);
+    free(Aq);
+    free(Bq);
+    return rc;
+}
+
 /* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *   C = alpha op(A) op(B) + beta C0.

@@ -532,6 +532,89 @@ def test_qtrmm_identity_and_alpha_zero():
     assert (qref.logical(z, M, N) == 0).all()
 
 
+# ---------------------------------------------------------------- mixed types
+def _plain_op(kind, op, X, rows, cols):
+    """Logical op(X) of a real ('R') or complex ('Z') stored matrix as a numpy
+    real or complex128 array (rows x cols)."""
+    sr, sc = (rows, cols) if op in "NR" else (cols, rows)
+    if kind == "R":
+        L = np.asarray(X)[:sc, :sr].T
+    else:
+        L = (np.asarray(X)[:sc, :sr, 0] + 1j * np.asarray(X)[:sc, :sr, 1]).T
+    if op in "TC":
+        L = L.T
+    if op in "CR":
+        L = np.conj(L)
+    return L
+
+
+def _qcomplex_pair(Q):
+    """(Q0 + i Q1, Q2 + i Q3) of a logical quaternion matrix (the split
+    q = q_0 + q_1 e2 into complex parts, Sec. 2.1)."""
+    return Q[..., 0] + 1j * Q[..., 1], Q[..., 2] + 1j * Q[..., 3]
+
+
+def _embed(kind, L):
+    """Logical quaternion matrix of a real or complex logical matrix (Eq. h_c_iso)."""
+    Q = np.zeros(L.shape + (4,))
+    Q[..., 0] = np.real(L)
+    if kind == "Z":
+        Q[..., 1] = np.imag(L)
+    return Q
+
+
+MIXED = [("Q", "R"), ("R", "Q"), ("Q", "Z"), ("Z", "Q")]
+
+
+@pytest.mark.parametrize("tA,tB", MIXED)
+@pytest.mark.parametrize("opA", "NTCR")
+@pytest.mark.parametrize("opB", "NTCR")
+def test_mixed_closed_forms(tA, tB, opA, opB):
+    """alpha = 1, beta = 0.  Quaternion x real: each component is a real
+    product; quaternion x complex: with a = a_0 + a_1 e2 and z e2 = e2 conj(z),
+    a z = a_0 z + a_1 conj(z) e2; complex x quaternion: z b = z b_0 + z b_1 e2."""
+    M, N, K = 4, 3, 5
+    p = W.mixed_problem(100 + MIXED.index((tA, tB)) * 16 + "NTCR".index(opA) * 4 + "NTCR".index(opB),
+                        tA, tB, M, N, K, opA, opB, dist="normal", pad=1)
+    got = qref.logical(oracle.qgemm_mixed(tA, tB, opA, opB, M, N, K, [1.0, 0, 0, 0], p["A"], p["lda"], p["B"],
+                                          p["ldb"], np.zeros(4), p["C"], p["ldc"]), M, N)
+    if tA == "Q":
+        QA = qref.apply_op(opA, p["A"], M, K)
+        Y = _plain_op(tB, opB, p["B"], K, N)
+        if tB == "R":
+            want = np.stack([QA[..., c] @ Y for c in range(4)], axis=-1)
+        else:
+            a0, a1 = _qcomplex_pair(QA)
+            c0, c1 = a0 @ Y, a1 @ np.conj(Y)
+            want = np.stack([c0.real, c0.imag, c1.real, c1.imag], axis=-1)
+    else:
+        QB = qref.apply_op(opB, p["B"], K, N)
+        Y = _plain_op(tA, opA, p["A"], M, K)
+        if tA == "R":
+            want = np.stack([Y @ QB[..., c] for c in range(4)], axis=-1)
+        else:
+            b0, b1 = _qcomplex_pair(QB)
+            c0, c1 = Y @ b0, Y @ b1
+            want = np.stack([c0.real, c0.imag, c1.real, c1.imag], axis=-1)
+    np.testing.assert_allclose(got, want, atol=1e-12)
+
+
+@pytest.mark.parametrize("tA,tB", MIXED)
+def test_mixed_scalars_vs_complex_embedding(tA, tB):
+    """Quaternion alpha and beta: the embedded product through the complex
+    block representation (Eq. hc_mat_mult)."""
+    M, N, K = 5, 4, 6
+    p = W.mixed_problem(170 + MIXED.index((tA, tB)), tA, tB, M, N, K, "C", "T", dist="normal")
+    got = qref.logical(oracle.qgemm_mixed(tA, tB, "C", "T", M, N, K, p["alpha"], p["A"], p["lda"], p["B"],
+                                          p["ldb"], p["beta"], p["C"], p["ldc"]), M, N)
+    LA = qref.apply_op("C", p["A"], M, K) if tA == "Q" else _embed(tA, _plain_op(tA, "C", p["A"], M, K))
+    LB = qref.apply_op("T", p["B"], K, N) if tB == "Q" else _embed(tB, _plain_op(tB, "T", p["B"], K, N))
+    SA = np.ascontiguousarray(LA.transpose(1, 0, 2))          # storage of op(A) as an N-op operand
+    SB = np.ascontiguousarray(LB.transpose(1, 0, 2))
+    want = qref.qgemm_via_complex("N", "N", M, N, K, p["alpha"], SA, SB, p["beta"], qref.logical(p["C"], M, N))
+    np.testing.assert_allclose(got, want, atol=1e-12)
+
+
 # ---------------------------------------------------------------- gradient
 def _loss(opA, opB, M, N, K, al, A, lda, B, ldb, G, be, C0):
     out = oracle.qgemm(opA, opB, M, N, K, al, A, lda, B, ldb, be, C0, M)
@@ -609,6 +692,8 @@ MUTANTS = [
     ("else           oracle_hamilton(B + 4 * (mu + ka * ldb), opt + 4 * (ka + nu * n), t);",
      "else           oracle_hamilton(opt + 4 * (ka + nu * n), B + 4 * (mu + ka * ldb), t);"),  # right side commuted
     ("oracle_hamilton(alpha, acc, C + 4 * (mu + nu * ldc));", "oracle_hamilton(acc, alpha, C + 4 * (mu + nu * ldc));"),  # trmm alpha right
+    ("Q[4 * (r + c * sr) + k] = X[type * (r + c * ldx) + k];",
+     "Q[4 * (r + c * sr) + (type == 2 ? 2 * k : k)] = X[type * (r + c * ldx) + k];"),  # complex into e0, e2
 ]
 
 
@@ -659,6 +744,16 @@ def _mutant_pins_fail(so):
                        P(t["alpha"]), P(t["A"]), t["lda"], P(t["B"]), t["ldb"], P(out), t["ldc"])
         if not np.allclose(qref.logical(out, 4, 5), _trmm_via_complex(t), atol=1e-12):
             return True
+    L.oracle_qgemm_mixed.argtypes = [ctypes.c_int] * 4 + [i64, i64, i64, dp, dp, i64, dp, i64, dp, dp, i64]
+    m = W.mixed_problem(9, "Z", "Q", 3, 4, 5, "N", "N", dist="normal")
+    out = np.zeros((4, 3, 4))
+    L.oracle_qgemm_mixed(2, 4, 0, 0, 3, 4, 5, P(np.array([1.0, 0, 0, 0])), P(m["A"]), m["lda"], P(m["B"]), m["ldb"],
+                         P(np.zeros(4)), P(out), 3)
+    Y = _plain_op("Z", "N", m["A"], 3, 5)
+    b0, b1 = _qcomplex_pair(qref.apply_op("N", m["B"], 5, 4))
+    c0, c1 = Y @ b0, Y @ b1
+    if not np.allclose(qref.logical(out, 3, 4), np.stack([c0.real, c0.imag, c1.real, c1.imag], axis=-1)):
+        return True
     return False
 
 

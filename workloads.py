@@ -106,6 +106,32 @@ def trmm_problem(seed, side, uplo, trans, diag, M, N, dist="uniform", dtype=np.f
                 C=C, ldc=ldc)
 
 
+def typed_matrix(g, kind, rows, cols, ld=None, dist="uniform", dtype=np.float64):
+    """Random matrix of element kind 'R' (real, storage (cols, ld)), 'Z'
+    (complex as interleaved (re, im), storage (cols, ld, 2)) or 'Q'
+    (quaternion, storage (cols, ld, 4)); padding rows hold NaN."""
+    width = {"R": 1, "Z": 2, "Q": 4}[kind]
+    ld = max(rows, 1) if ld is None else ld
+    v = g.uniform(-1.0, 1.0, (cols, rows, width)) if dist == "uniform" else g.standard_normal((cols, rows, width))
+    out = np.full((cols, ld, width), np.nan, dtype=dtype)
+    out[:, :rows, :] = v.astype(dtype)
+    return out[..., 0] if kind == "R" else out
+
+
+def mixed_problem(seed, typeA, typeB, M, N, K, opA="N", opB="N", dist="uniform", pad=0):
+    """Mixed-type GEMM inputs: A of kind typeA, B of kind typeB (see
+    typed_matrix), quaternion C and random quaternion alpha, beta."""
+    g = rng(seed)
+    ra, ca = stored_dims(opA, M, K)
+    rb, cb = stored_dims(opB, K, N)
+    lda, ldb, ldc = max(ra, 1) + pad, max(rb, 1) + pad, max(M, 1) + pad
+    A = typed_matrix(g, typeA, ra, ca, ld=lda, dist=dist)
+    B = typed_matrix(g, typeB, rb, cb, ld=ldb, dist=dist)
+    C = qmatrix(g, M, N, ld=ldc, dist=dist)
+    return dict(typeA=typeA, typeB=typeB, opA=opA, opB=opB, M=M, N=N, K=K, alpha=quaternion(g),
+                beta=quaternion(g), A=A, lda=lda, B=B, ldb=ldb, C=C, ldc=ldc)
+
+
 SWEEP_SIZES = (1024, 2048, 4096, 8192)
 OP_PAIRS = tuple((a, b) for a in "NTC" for b in "NTC")
 
