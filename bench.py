@@ -18,7 +18,7 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    rate and its error against the oracle on sampled outputs.
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
-    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm    one part, no CPU baseline
+    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed    one part, no CPU baseline
 """
 import argparse
 import hashlib
@@ -316,6 +316,40 @@ def variant_trmm(steps, warmup):
                                           "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}}
 
 
+def variant_mixed(steps, warmup):
+    """Mixed-type GEMM qgemm_mixed_d, FP64 M = N = K = 8192 op N/N: quaternion
+    x real (4 real multiply-adds per element product, 8 MNK flops) and complex
+    x quaternion (8 multiply-adds, 16 MNK flops); error on a 64 x 32 sample
+    against the oracle's qgemm_mixed."""
+    import oracle
+    n = 8192
+    out = {}
+    for tA, tB, fpm, name in (("Q", "R", 8, "fp64_mixed_8192_quat_x_real"),
+                              ("Z", "Q", 16, "fp64_mixed_8192_complex_x_quat")):
+        p = W.mixed_problem(W.BASE_SEED + 9 + fpm, tA, tB, n, n, n)
+        A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
+        C0 = C.clone()
+        _, ev = time_launches(lambda: q.qgemm_mixed(tA, tB, "N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),
+                              steps, warmup)
+        C.copy_(C0)
+        q.qgemm_mixed(tA, tB, "N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n)
+        gs = np.random.default_rng(10)
+        rows = np.sort(gs.choice(n, 64, replace=False))
+        cols = np.sort(gs.choice(n, 32, replace=False))
+        As = np.ascontiguousarray(p["A"][:, rows])
+        Bs = np.ascontiguousarray(p["B"][cols])
+        Cs = np.ascontiguousarray(p["C"][cols][:, rows])
+        want = oracle.qgemm_mixed(tA, tB, "N", "N", 64, 32, n, p["alpha"], As, 64, Bs, n, p["beta"], Cs, 64)
+        got = C.cpu().numpy()[cols][:, rows]
+        fl = fpm * n * n * n
+        out[name] = {"ms": round(ev, 3), "tflops_useful": round(fl / (ev * 1e-3) / 1e12, 2),
+                     "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4),
+                     "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}
+        del A, B, C, C0
+        torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -336,7 +370,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -351,9 +385,10 @@ def main():
         calibrate_copy()
         return
 
-    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm"):
+    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm", "mixed"):
         fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
-              "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm}[args.only]
+              "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm,
+              "mixed": variant_mixed}[args.only]
         print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
@@ -403,7 +438,8 @@ def main():
     if not args.no_variants:
         variants = {}
         for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
-                         ("scalars", variant_scalars), ("herk", variant_herk), ("trmm", variant_trmm)):
+                         ("scalars", variant_scalars), ("herk", variant_herk), ("trmm", variant_trmm),
+                         ("mixed", variant_mixed)):
             log(f"[bench] variant {name}")
             variants.update(fn(args.steps, args.warmup))
             torch.cuda.empty_cache()

@@ -68,6 +68,12 @@ typedef enum {
 } qgemm_uplo_t;
 
 typedef enum {
+    QGEMM_REAL = 1,
+    QGEMM_COMPLEX = 2,
+    QGEMM_QUATERNION = 4
+} qgemm_type_t;
+
+typedef enum {
     QGEMM_SIDE_LEFT = 0,
     QGEMM_SIDE_RIGHT = 1
 } qgemm_side_t;
@@ -215,6 +221,31 @@ qgemm_status_t qtrmm_s(int side, int uplo, int trans, int diag, int64_t M, int64
                        const double *alpha, const float *A, int64_t lda,
                        const float *B, int64_t ldb, float *C, int64_t ldc,
                        int split_terms, void *stream);
+
+/*
+ * qgemm_mixed_d -- mixed-type GEMM (the quaternion-real and
+ * quaternion-complex arithmetic the paper's library provides, Sec. 5):
+ *     C <- alpha op(A) op(B) + beta C
+ * with one of A, B real or complex and the other quaternion; C, alpha and
+ * beta are quaternions (alpha, beta from the left).  typeA / typeB give the
+ * element kind and so the reals per stored element: QGEMM_REAL (1 double),
+ * QGEMM_COMPLEX (2 doubles, re then im), QGEMM_QUATERNION (4 doubles).  Leading
+ * dimensions count elements.  A real x enters as x e0 and a complex z0 + z1 i
+ * as z0 e0 + z1 e1 (Eq. complex_subalg, Eq. h_c_iso); op T transposes, C
+ * conjugate-transposes, R conjugates (a no-op on a real operand, complex
+ * conjugation on a complex one).  Both quaternion: same as qgemm_d.  Neither
+ * quaternion: QGEMM_ERR_INVALID_ARG (argument 2).  The embedded operand is
+ * never widened: a real operand costs 4 and a complex one 8 real
+ * multiply-adds per element product (16 for quaternion x quaternion).
+ * Alignment: one element of each operand (8, 16 or 32 bytes).  Quick returns
+ * and beta == 0 / alpha == 0 rules as qgemm_d.
+ * Arguments: 1 typeA, 2 typeB, 3 opA, 4 opB, 5 M, 6 N, 7 K, 8 alpha, 9 A,
+ *   10 lda, 11 B, 12 ldb, 13 beta, 14 C, 15 ldc, then stream.
+ */
+qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, int64_t N, int64_t K,
+                             const double *alpha, const double *A, int64_t lda,
+                             const double *B, int64_t ldb, const double *beta,
+                             double *C, int64_t ldc, void *stream);
 
 /*
  * Grouped (batched) FP32 quaternion GEMM: many independent problems

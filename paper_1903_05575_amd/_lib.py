@@ -54,6 +54,8 @@ _SIGNATURES = {
     "qherk_s": ([_int, _int, _i64, _i64, ctypes.c_double, _vp, _i64, ctypes.c_double, _vp, _i64, _int, _vp], _int),
     "qtrmm_d": ([_int, _int, _int, _int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _vp], _int),
     "qtrmm_s": ([_int, _int, _int, _int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp], _int),
+    "qgemm_mixed_d": ([_int, _int, _int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp],
+                      _int),
     "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
                                    _int, _int], _int),
     "qgemm_batched_run": ([_vp, _vp], _int),
@@ -103,8 +105,9 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-def _check_storage(t, rows, cols, ld, dtype, name):
-    """A stored rows x cols operand needs (cols-1)*ld + rows quaternions."""
+def _check_storage(t, rows, cols, ld, dtype, name, width=4):
+    """A stored rows x cols operand needs (cols-1)*ld + rows elements of
+    `width` reals (4 for a quaternion)."""
     if rows == 0 or cols == 0:
         return
     if t is None:
@@ -115,7 +118,7 @@ def _check_storage(t, rows, cols, ld, dtype, name):
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    need = 4 * ((cols - 1) * ld + rows)
+    need = width * ((cols - 1) * ld + rows)
     if t.numel() < need:
         raise ValueError(f"{name} holds {t.numel()} reals, needs {need}")
 
@@ -331,3 +334,23 @@ def qtrmm(side, uplo, trans, diag, M, N, alpha, A, lda, B, ldb, C, ldc, split_te
         _raise(lib().qtrmm_s(*args, int(split_terms), _stream(stream)), "qtrmm_s")
     else:
         raise ValueError(f"unsupported dtype {dtype}")
+
+
+TYPES = {"R": 1, "Z": 2, "Q": 4}
+
+
+def qgemm_mixed(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    """Mixed-type GEMM in binary64 (C-ABI qgemm_mixed_d): one of A, B real
+    ('R', tensor (cols, ld)) or complex ('Z', (cols, ld, 2)), the other
+    quaternion ('Q', (cols, ld, 4)); C quaternion."""
+    ra, ca = _stored(opA, M, K)
+    rb, cb = _stored(opB, K, N)
+    if M and N and K:
+        _check_storage(A, ra, ca, lda, torch.float64, "A", TYPES[typeA])
+        _check_storage(B, rb, cb, ldb, torch.float64, "B", TYPES[typeB])
+    _check_storage(C, M, N, ldc, torch.float64, "C")
+    pa, _ka = _q4(alpha)
+    pb, _kb = _q4(beta)
+    rc = lib().qgemm_mixed_d(TYPES[typeA], TYPES[typeB], OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb,
+                             pb, _ptr(C), ldc, _stream(stream))
+    _raise(rc, "qgemm_mixed_d")

@@ -476,6 +476,50 @@ qgemm_status_t qtrmm_s(int side, int uplo, int trans, int diag, int64_t M, int64
                             static_cast<hipStream_t>(stream));
 }
 
+qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, int64_t N, int64_t K,
+                             const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                             const double *beta, double *C, int64_t ldc, void *stream)
+{
+    g_bad_arg = 0;
+    auto valid_type = [](int t) { return t == QGEMM_REAL || t == QGEMM_COMPLEX || t == QGEMM_QUATERNION; };
+    if (!valid_type(typeA)) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (!valid_type(typeB)) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (typeA != QGEMM_QUATERNION && typeB != QGEMM_QUATERNION) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 8);
+    if (s != QGEMM_OK) return fail(s, g_bad_arg + 2);
+    if (M == 0 || N == 0) return QGEMM_OK;
+    const bool reads_ab = K > 0 && !is_zero4(alpha);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(A) % (8u * typeA))) return fail(QGEMM_ERR_MISALIGNED, 9);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(B) % (8u * typeB))) return fail(QGEMM_ERR_MISALIGNED, 11);
+    if (reinterpret_cast<uintptr_t>(C) % 32u) return fail(QGEMM_ERR_MISALIGNED, 14);
+    if (typeA == QGEMM_QUATERNION && typeB == QGEMM_QUATERNION) {
+        s = qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+        return s == QGEMM_OK ? s : fail(s, g_bad_arg + 2);
+    }
+    qg::MixedDesc d{};
+    const bool right = typeB == QGEMM_QUATERNION;   // quaternion is the right factor: out = C^T
+    d.right = right;
+    d.C = C;
+    d.ldc = ldc;
+    d.K = (int)K;
+    if (!right) {
+        d.X = A; d.ldx = lda; d.P = (int)M; d.xt = op_transposes(opA); d.conjX = op_conjugates(opA);
+        d.Y = B; d.ldy = ldb; d.Q = (int)N; d.yt = op_transposes(opB); d.conjY = typeB == QGEMM_COMPLEX && op_conjugates(opB);
+        d.kc = typeB;
+    } else {
+        d.X = B; d.ldx = ldb; d.P = (int)N; d.xt = !op_transposes(opB); d.conjX = op_conjugates(opB);
+        d.Y = A; d.ldy = lda; d.Q = (int)M; d.yt = !op_transposes(opA); d.conjY = typeA == QGEMM_COMPLEX && op_conjugates(opA);
+        d.kc = typeA;
+    }
+    for (int i = 0; i < 4; ++i) {
+        d.alpha[i] = alpha[i];
+        d.beta[i] = beta[i];
+    }
+    if (!qg::mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc)) return fail(QGEMM_ERR_UNSUPPORTED, right ? 12 : 10);
+    if (qg::launch_qgemm_mixed_f64(d, static_cast<hipStream_t>(stream)) != hipSuccess) return QGEMM_ERR_HIP;
+    return QGEMM_OK;
+}
+
 qgemm_status_t qgemm_backward_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
                                 const double *A, int64_t lda, const double *B, int64_t ldb, const double *G,
                                 int64_t ldg, const double *beta, double *dA, int64_t ldda, double *dB,

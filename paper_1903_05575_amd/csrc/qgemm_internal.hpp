@@ -69,6 +69,27 @@ inline bool split_ld_supported(int64_t lda, int64_t ldb, bool ta, bool tb)
     const int64_t fb = 16 * (tb ? (16 * ldb + 64) : (64 * ldb + 16));
     return fa < lim && fb < lim;
 }
+// One mixed-type FP64 launch (qgemm_mixed_f64.hip): out = X . Y with X a
+// quaternion operand (P x K after its op) and Y a real (kc = 1) or complex
+// (kc = 2, re/im interleaved) operand (K x Q after its op); out is C, or C^T
+// when `right` (the quaternion is the right factor of C = op(A) op(B)).
+struct MixedDesc {
+    const double *X;
+    const double *Y;
+    double *C;
+    int64_t ldx, ldy, ldc;
+    int P, Q, K;
+    int kc;
+    bool right;
+    bool xt;               // X stored with kappa contiguous: X[kappa + p ldx], else X[p + kappa ldx]
+    bool yt;               // Y stored with q contiguous: Y[q + kappa ldy], else Y[kappa + q ldy]
+    bool conjX, conjY;     // conjugate X (quaternion) / Y (complex) as read
+    double alpha[4];
+    double beta[4];
+};
+bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc);
+hipError_t launch_qgemm_mixed_f64(const MixedDesc &d, hipStream_t stream);
+
 // Grouped (batched) split-BF16 plans; see qgemm_grouped.hip.
 struct GroupedPlan;
 constexpr int kGroupedClasses = 5;

@@ -1,0 +1,291 @@
+// FP64 mixed-type quaternion GEMM on the gfx950 FP64 matrix cores: one
+// operand real or complex, the other quaternion, C quaternion.  A real x is
+// the quaternion x e0 and a complex z0 + z1 i the quaternion z0 e0 + z1 e1
+// (the complex subalgebra, Eq. complex_subalg and Eq. h_c_iso).
+//
+// Method.  The embedded operand is never widened into quaternions: that
+// would feed the matrix cores 3 zeros of 4 (real) or 1 of 2 (complex).  The
+// product is instead a real contraction over kappa (real operand) or over
+// (kappa, s), s = re / im (complex operand), from Eq. quaternion_prod:
+//   x y, y real             : (x y)_r = x_r y
+//   x z, quaternion on left : x z = z0 x + z1 (x e1),  x e1 = (-x1,  x0,  x3, -x2)
+//   z x, quaternion on right: z x = z0 x + z1 (e1 x),  e1 x = (-x1,  x0, -x3,  x2)
+// so a real operand costs 4 and a complex one 8 real multiply-adds per
+// element product (against 16 for two quaternions).
+//
+// Roles.  The quaternion operand X (P x K) is the MFMA A operand, expanded
+// per lane by a component index and a sign as in the quaternion kernel; the
+// real or complex operand Y (K x Q, KC = 1 or 2 reals per element) is the
+// MFMA B operand exactly as stored.  out = X . Y is C itself when the
+// quaternion is the left factor (P = M, Q = N) and C^T when it is the right
+// factor (P = N, Q = M; C = Y X, read as out[nu][mu] = sum X[nu][k] . Y[k][mu]
+// with Y the left factor of each product).
+//
+// MFMA v_mfma_f64_16x16x4_f64 (layout as in qgemm_f64.hip): A row i is
+// quaternion row p = i % 4 and component r = i / 4 of the result; A column k
+// is kappa = k (KC = 1) or (kappa, s) = (k / 2, k % 2) (KC = 2).  Lane l of
+// the result holds all four components of out(p0 + l / 16, q0 + l % 16), so
+// the alpha / beta epilogue is lane-local.
+//
+// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 128
+// quaternions of out.  Wave w owns rows [8w, 8w + 8) x all 128 columns = 2 x
+// 8 MFMA blocks.  A K-tile is 4 MFMA k-steps (16 kappa for a real, 8 for a
+// complex operand), staged through two LDS stages; the next K-tile is loaded
+// at the start of a tile and written to the other stage after the third
+// k-step.  Masked elements use the out-of-range buffer offset that reads as
+// zero, so the K-loop has no branches.
+// LDS layouts (doubles):
+//   X stage: [kappa][p][4], row pitch 4 BP + 4
+//   Y stage: [kappa * KC + s][q], row pitch BQ + 1
+#include "qgemm_internal.hpp"
+
+#include <type_traits>
+
+namespace qg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int BP = 32, BQ = 128, NT = 256, STEPS = 4;
+constexpr int XP = 4 * BP + 4;      // doubles per kappa row of the X stage
+constexpr int YP = BQ + 1;          // doubles per row of the Y stage
+constexpr unsigned kOob = 0x80000000u;
+
+template <int KC>
+struct Shape {
+    static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
+    static constexpr int X_STAGE = BK * XP;
+    static constexpr int Y_STAGE = BK * KC * YP;
+    static constexpr int STAGE = X_STAGE + Y_STAGE;
+    static constexpr int X_CH = BP * BK * 2 / NT;              // 16-byte halves of X per thread
+    static constexpr int Y_EL = BK * BQ / NT;                  // Y elements per thread
+    static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
+    static_assert(X_CH * NT == BP * BK * 2, "X tile must split evenly");
+    static_assert(Y_EL * NT == BK * BQ, "Y tile must split evenly");
+};
+
+__device__ __forceinline__ double flip(double v, bool neg)
+{
+    return __longlong_as_double(__double_as_longlong(v) ^ (neg ? (long long)0x8000000000000000ull : 0ll));
+}
+
+template <int KC, bool RIGHT, bool XT, bool YT>
+__global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int tiles_p, int tiles_q, int nk)
+{
+    using S = Shape<KC>;
+    constexpr int BK = S::BK;
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    int tp, tq;
+    xcd_tile(blockIdx.x, gridDim.x, tiles_p, tiles_q, 8, tp, tq);
+    const int p0 = tp * BP, q0 = tq * BQ;
+
+    // ---- per-lane constants of the A fragment (row i = lane % 16, column k = lane / 16)
+    const int fi = lane & 15;
+    const int fr = fi >> 2;                       // component of the result
+    const int fp = fi & 3;                        // quaternion row within the 4-row block
+    const int fk = lane >> 4;
+    const int fs = KC == 2 ? (fk & 1) : 0;        // re / im of the complex operand
+    const int fcomp = fr ^ fs;                    // component of x feeding this lane
+    // sign of the e1 column: x e1 negates rows 0 and 3, e1 x rows 0 and 2
+    const bool e1neg = fs == 1 && (fr == 0 || fr == (RIGHT ? 2 : 3));
+    const bool neg = e1neg ^ (p.conjX && fcomp != 0) ^ (p.conjY && fs == 1);
+    const int x_off = (fk / KC) * XP + (wave * 8 + fp) * 4 + fcomp;   // + step * (4 / KC) * XP + 16 m
+    const int y_off = fk * YP + fi;                                     // + step * 4 * YP + 16 n
+
+    d4 acc[2][8];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 8; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    d2 rx[S::X_CH];
+    typedef typename std::conditional<KC == 1, double, d2>::type YT_t;
+    YT_t ry[S::Y_EL];
+
+    auto x_slot = [&](int i, int &pp, int &ka, int &half) {
+        const int q = tid + NT * i;
+        half = q & 1;
+        if (!XT) { pp = (q >> 1) % BP; ka = (q >> 1) / BP; }
+        else     { ka = (q >> 1) % BK; pp = (q >> 1) / BK; }
+    };
+    auto y_slot = [&](int i, int &ka, int &qq) {
+        const int e = tid + NT * i;
+        if (!YT) { ka = e % BK; qq = e / BK; }
+        else     { qq = e % BQ; ka = e / BQ; }
+    };
+
+    auto load_tile = [&](int kt) {
+        const int k0 = kt * BK;
+        const int krem = p.K - k0;
+        const double *Xb = p.X + 4 * (XT ? ((int64_t)p0 * p.ldx + k0) : ((int64_t)k0 * p.ldx + p0));
+        const double *Yb = p.Y + KC * (YT ? ((int64_t)k0 * p.ldy + q0) : ((int64_t)q0 * p.ldy + k0));
+        const __amdgpu_buffer_rsrc_t rX = __builtin_amdgcn_make_buffer_rsrc((void *)Xb, (short)0, 0x7fffffff, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rY = __builtin_amdgcn_make_buffer_rsrc((void *)Yb, (short)0, 0x7fffffff, 0x00020000);
+#pragma unroll
+        for (int i = 0; i < S::X_CH; ++i) {
+            int pp, ka, half;
+            x_slot(i, pp, ka, half);
+            const unsigned e = XT ? (unsigned)pp * (unsigned)p.ldx + ka : (unsigned)ka * (unsigned)p.ldx + pp;
+            const bool ok = p0 + pp < p.P && ka < krem;
+            rx[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rX, ok ? 32u * e + 16u * half : kOob, 0, 0));
+        }
+#pragma unroll
+        for (int i = 0; i < S::Y_EL; ++i) {
+            int ka, qq;
+            y_slot(i, ka, qq);
+            const unsigned e = YT ? (unsigned)ka * (unsigned)p.ldy + qq : (unsigned)qq * (unsigned)p.ldy + ka;
+            const bool ok = q0 + qq < p.Q && ka < krem;
+            const unsigned o = ok ? (unsigned)(8 * KC) * e : kOob;
+            if constexpr (KC == 1) ry[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rY, o, 0, 0));
+            else ry[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rY, o, 0, 0));
+        }
+    };
+
+    auto store_tile = [&](double *Xs) {
+        double *Ys = Xs + S::X_STAGE;
+#pragma unroll
+        for (int i = 0; i < S::X_CH; ++i) {
+            int pp, ka, half;
+            x_slot(i, pp, ka, half);
+            *reinterpret_cast<d2 *>(Xs + ka * XP + pp * 4 + 2 * half) = rx[i];
+        }
+#pragma unroll
+        for (int i = 0; i < S::Y_EL; ++i) {
+            int ka, qq;
+            y_slot(i, ka, qq);
+            if constexpr (KC == 1) {
+                Ys[ka * YP + qq] = ry[i];
+            } else {
+                Ys[(2 * ka) * YP + qq] = ry[i].x;
+                Ys[(2 * ka + 1) * YP + qq] = ry[i].y;
+            }
+        }
+    };
+
+    // Multiply the K-tile in stage `Xs`; the registers of the next K-tile are
+    // written to `Nxt` after the third k-step.  Fragments of step kk + 1 are
+    // read while step kk's 16 MFMAs run.
+    auto step_tile = [&](const double *Xs, double *Nxt) {
+        const double *Ys = Xs + S::X_STAGE;
+        double a[2][2], b[2][8];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) a[0][m] = Xs[x_off + 16 * m];
+#pragma unroll
+        for (int n = 0; n < 8; ++n) b[0][n] = Ys[y_off + 16 * n];
+#pragma unroll
+        for (int kk = 0; kk < STEPS; ++kk) {
+            const int cur = kk & 1;
+            if (kk + 1 < STEPS) {
+#pragma unroll
+                for (int m = 0; m < 2; ++m) a[cur ^ 1][m] = Xs[(kk + 1) * (4 / KC) * XP + x_off + 16 * m];
+#pragma unroll
+                for (int n = 0; n < 8; ++n) b[cur ^ 1][n] = Ys[(kk + 1) * 4 * YP + y_off + 16 * n];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const double am = flip(a[cur][m], neg);
+#pragma unroll
+                for (int n = 0; n < 8; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (kk == STEPS - 2) store_tile(Nxt);
+        }
+    };
+
+    if (nk > 0) {
+        load_tile(0);
+        store_tile(smem);
+        __syncthreads();
+    }
+    // tiles past the end load as zeros and land in the unused stage
+    for (int kt = 0; kt < nk; ++kt) {
+        const int st = kt & 1;
+        load_tile(kt + 1);
+        step_tile(smem + st * S::STAGE, smem + (st ^ 1) * S::STAGE);
+        __syncthreads();
+    }
+
+    // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions
+    const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int pp = p0 + wave * 8 + 4 * m + (lane >> 4);
+#pragma unroll
+        for (int n = 0; n < 8; ++n) {
+            const int qq = q0 + 16 * n + (lane & 15);
+            if (pp >= p.P || qq >= p.Q) continue;
+            const int mu = RIGHT ? qq : pp, nu = RIGHT ? pp : qq;
+            const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
+            double o[4];
+            qmul(p.alpha, v, o);
+            d2 *dst = reinterpret_cast<d2 *>(p.C + 4 * ((int64_t)nu * p.ldc + mu));
+            if (!beta_zero) {
+                const d2 c0 = dst[0], c1 = dst[1];
+                const double cq[4] = {c0.x, c0.y, c1.x, c1.y};
+                double u[4];
+                qmul(p.beta, cq, u);
+                o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
+            }
+            dst[0] = (d2){o[0], o[1]};
+            dst[1] = (d2){o[2], o[3]};
+        }
+    }
+}
+
+template <int KC, bool RIGHT, bool XT, bool YT>
+hipError_t launch_t(const MixedDesc &d, hipStream_t stream)
+{
+    using S = Shape<KC>;
+    auto kern = &qgemm_mixed_f64_kernel<KC, RIGHT, XT, YT>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int tiles_p = (d.P + BP - 1) / BP;
+    const int tiles_q = (d.Q + BQ - 1) / BQ;
+    const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
+    const int nk = alpha_zero ? 0 : (d.K + S::BK - 1) / S::BK;
+    const int64_t nblocks = (int64_t)tiles_p * tiles_q;
+    if (nblocks <= 0) return hipSuccess;
+    if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(NT), S::LDS_BYTES, stream, d, tiles_p, tiles_q, nk);
+    return hipGetLastError();
+}
+
+template <int KC, bool RIGHT>
+hipError_t launch_layouts(const MixedDesc &d, hipStream_t s)
+{
+    if (d.xt) return d.yt ? launch_t<KC, RIGHT, true, true>(d, s) : launch_t<KC, RIGHT, true, false>(d, s);
+    return d.yt ? launch_t<KC, RIGHT, false, true>(d, s) : launch_t<KC, RIGHT, false, false>(d, s);
+}
+
+}  // namespace
+
+bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc)
+{
+    const int64_t lim = (int64_t)1 << 31;
+    const int bk = STEPS * 4 / kc;
+    const int64_t fx = 32 * (xt ? ((int64_t)BP * ldx + bk) : ((int64_t)bk * ldx + BP));
+    const int64_t fy = 8 * kc * (yt ? ((int64_t)bk * ldy + BQ) : ((int64_t)BQ * ldy + bk));
+    return fx < lim && fy < lim;
+}
+
+hipError_t launch_qgemm_mixed_f64(const MixedDesc &d, hipStream_t stream)
+{
+    if (!mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc)) return hipErrorInvalidValue;
+    if (d.kc == 1) return d.right ? launch_layouts<1, true>(d, stream) : launch_layouts<1, false>(d, stream);
+    if (d.kc == 2) return d.right ? launch_layouts<2, true>(d, stream) : launch_layouts<2, false>(d, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace qg

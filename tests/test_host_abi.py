@@ -197,3 +197,27 @@ def test_validation_trmm_s_and_quick_return(L):
     # empty output: nothing read or written
     assert call_trmm(L, M=0, A=None, B=None, C=None) == 0
     assert call_trmm(L, N=0, A=None, B=None, C=None) == 0
+
+
+def call_mixed(L, tA=4, tB=1, opA=0, opB=0, M=4, N=4, K=4, alpha=ONE, A=FAKE, lda=4, B=FAKE_B, ldb=4, beta=ONE,
+               C=FAKE_C, ldc=4):
+    return L.qgemm_mixed_d(tA, tB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, None)
+
+
+@pytest.mark.parametrize("kw,arg,status", [
+    (dict(tA=3), 1, 1), (dict(tB=0), 2, 1), (dict(tA=1, tB=2), 2, 1), (dict(opA=5), 3, 1), (dict(opB=-1), 4, 1),
+    (dict(M=-1), 5, 1), (dict(K=-1), 7, 1), (dict(alpha=None), 8, 1), (dict(lda=3), 10, 1), (dict(ldb=3), 12, 1),
+    (dict(beta=None), 13, 1), (dict(ldc=3), 15, 1), (dict(A=None), 9, 1), (dict(B=None), 11, 1),
+    (dict(C=None), 14, 1), (dict(A=FAKE + 8), 9, 2), (dict(tA=2, tB=4, A=FAKE + 8), 9, 2),
+    (dict(B=FAKE_B + 4), 11, 2), (dict(C=FAKE_C + 16), 14, 2),
+])
+def test_validation_mixed(L, kw, arg, status):
+    """qgemm_mixed_d numbering: 1 typeA, 2 typeB, then as qgemm_d shifted by two;
+    the element of each operand sets its alignment (8, 16, 32 bytes)."""
+    assert call_mixed(L, **kw) == status
+    assert L.qgemm_last_invalid_arg() == arg
+
+
+def test_mixed_real_alignment_is_one_double(L):
+    # a real B at an 8-byte offset is aligned; the call then fails later on the misaligned quaternion C
+    assert call_mixed(L, B=FAKE_B + 8, C=FAKE_C + 8) == 2 and L.qgemm_last_invalid_arg() == 14
