@@ -69,6 +69,12 @@ def lib():
         L.oracle_qtrmm.restype = ctypes.c_int
         L.oracle_qgemm_mixed.argtypes = [ctypes.c_int] * 4 + [i64, i64, i64, dp, dp, i64, dp, i64, dp, dp, i64]
         L.oracle_qgemm_mixed.restype = ctypes.c_int
+        L.oracle_qaxpy.argtypes = [i64, dp, dp, i64, dp, i64]
+        L.oracle_qaxpy.restype = ctypes.c_int
+        L.oracle_qdot.argtypes = [ctypes.c_int, i64, dp, i64, dp, i64, dp]
+        L.oracle_qdot.restype = ctypes.c_int
+        L.oracle_qgemv.argtypes = [ctypes.c_int, i64, i64, dp, dp, i64, dp, i64, dp, dp, i64]
+        L.oracle_qgemv.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_set_threads.restype = None
         L.oracle_max_threads.argtypes = []
@@ -179,6 +185,32 @@ def qgemm_mixed(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C,
                                   _ptr(A), lda, _ptr(B), ldb, _ptr(_f64(beta)), _ptr(out), ldc)
     if rc != 0:
         raise RuntimeError(f"oracle_qgemm_mixed failed ({rc})")
+    return out
+
+
+def qaxpy(n, alpha, x, incx, y, incy):
+    """alpha x + y over n strided quaternions; x, y are (len, 4) arrays.  Returns a new y."""
+    x = _f64(x)
+    out = _f64(y).copy()
+    if lib().oracle_qaxpy(n, _ptr(_f64(alpha)), _ptr(x), incx, _ptr(out), incy) != 0:
+        raise RuntimeError("oracle_qaxpy failed")
+    return out
+
+
+def qdot(conj, n, x, incx, y, incy):
+    """sum x_i y_i (conj: sum conj(x_i) y_i) as a length-4 array."""
+    r = np.zeros(4)
+    if lib().oracle_qdot(int(bool(conj)), n, _ptr(_f64(x)), incx, _ptr(_f64(y)), incy, _ptr(r)) != 0:
+        raise RuntimeError("oracle_qdot failed")
+    return r
+
+
+def qgemv(trans, M, N, alpha, A, lda, x, incx, beta, y, incy):
+    """alpha op(A) x + beta y with A stored M x N; returns a new y."""
+    out = _f64(y).copy()
+    if lib().oracle_qgemv(OPS[trans], M, N, _ptr(_f64(alpha)), _ptr(_f64(A)), lda, _ptr(_f64(x)), incx,
+                          _ptr(_f64(beta)), _ptr(out), incy) != 0:
+        raise RuntimeError("oracle_qgemv failed")
     return out
 
 

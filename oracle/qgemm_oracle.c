@@ -362,6 +362,68 @@ int oracle_qgemm_mixed(int typeA, int typeB, int opA, int opB, int64_t M, int64_
     return rc;
 }
 
+/* Level-1/2 operations of the quaternion BLAS (the library scope of Sec. 5),
+ * as plain loops in the BLAS conventions; vectors are strided by inc >= 1
+ * elements, scalars multiply from the left as in Eq. general_gemm.
+ *   qaxpy: y_i <- alpha x_i + y_i
+ *   qdot : r = sum_i x_i y_i, or sum_i conj(x_i) y_i when conj != 0
+ *   qgemv: y <- alpha op(A) x + beta y, A stored M x N; op(A) is M x N (N, R)
+ *          or N x M (T, C); beta == 0: y not read; alpha == 0: A, x not read.
+ * Returns 0, or -2 on a bad argument. */
+int oracle_qaxpy(int64_t n, const double *alpha, const double *x, int64_t incx, double *y, int64_t incy)
+{
+    if (incx < 1 || incy < 1) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        double t[4];
+        oracle_hamilton(alpha, x + 4 * i * incx, t);
+        for (int c = 0; c < 4; ++c) y[4 * i * incy + c] += t[c];
+    }
+    return 0;
+}
+
+int oracle_qdot(int conj, int64_t n, const double *x, int64_t incx, const double *y, int64_t incy,
+                double *result)
+{
+    if (incx < 1 || incy < 1) return -2;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        double xi[4], t[4];
+        if (conj) conj_q(x + 4 * i * incx, xi);
+        else memcpy(xi, x + 4 * i * incx, sizeof xi);
+        oracle_hamilton(xi, y + 4 * i * incy, t);
+        for (int c = 0; c < 4; ++c) acc[c] += t[c];
+    }
+    memcpy(result, acc, sizeof acc);
+    return 0;
+}
+
+int oracle_qgemv(int trans, int64_t M, int64_t N, const double *alpha, const double *A, int64_t lda,
+                 const double *x, int64_t incx, const double *beta, double *y, int64_t incy)
+{
+    if (trans < 0 || trans > 3 || incx < 1 || incy < 1) return -2;
+    const int64_t rows = (trans == 0 || trans == 3) ? M : N, cols = (trans == 0 || trans == 3) ? N : M;
+    if (rows <= 0) return 0;
+    const int alpha_zero = alpha[0] == 0.0 && alpha[1] == 0.0 && alpha[2] == 0.0 && alpha[3] == 0.0;
+    const int beta_zero = beta[0] == 0.0 && beta[1] == 0.0 && beta[2] == 0.0 && beta[3] == 0.0;
+    double *opa = materialise_op(trans, rows, alpha_zero ? 0 : cols, A, lda);
+    if (!opa) return -1;
+    for (int64_t r = 0; r < rows; ++r) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t c = 0; c < (alpha_zero ? 0 : cols); ++c) {
+            double t[4];
+            oracle_hamilton(opa + 4 * (r + c * rows), x + 4 * c * incx, t);
+            for (int k = 0; k < 4; ++k) acc[k] += t[k];
+        }
+        double *yr = y + 4 * r * incy;
+        double s[4], u[4] = {0.0, 0.0, 0.0, 0.0};
+        oracle_hamilton(alpha, acc, s);
+        if (!beta_zero) oracle_hamilton(beta, yr, u);
+        for (int k = 0; k < 4; ++k) yr[k] = s[k] + u[k];
+    }
+    free(opa);
+    return 0;
+}
+
 /* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *   C = alpha op(A) op(B) + beta C0.

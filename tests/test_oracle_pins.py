@@ -615,6 +615,57 @@ def test_mixed_scalars_vs_complex_embedding(tA, tB):
     np.testing.assert_allclose(got, want, atol=1e-12)
 
 
+# ---------------------------------------------------------------- level 1 / 2
+def test_qaxpy_brute_force():
+    """alpha x_i + y_i element by element through the basis table, strided
+    vectors with NaN between the elements."""
+    g = W.rng(200)
+    n = 9
+    x, y = W.qvector(g, n, 3), W.qvector(g, n, 2)
+    al = W.quaternion(g)
+    got = oracle.qaxpy(n, al, x, 3, y, 2)
+    for i in range(n):
+        np.testing.assert_allclose(got[2 * i], np.asarray(qref.bf_mul(al, x[3 * i])) + y[2 * i], atol=1e-14)
+    assert np.isnan(got[1::2]).all()
+
+
+@pytest.mark.parametrize("conj", [False, True])
+def test_qdot_vs_complex_embedding(conj):
+    """sum x_i y_i (or conj(x_i) y_i) is the 1 x n by n x 1 product op(X) Y
+    with op T (C), evaluated on the complex block representation."""
+    g = W.rng(201 + conj)
+    n = 11
+    x, y = W.qvector(g, n, 2), W.qvector(g, n, 1)
+    got = oracle.qdot(conj, n, x, 2, y, 1)
+    X = np.ascontiguousarray(x[::2][:n][None])          # stored n x 1 (one column)
+    Y = np.ascontiguousarray(y[None])
+    want = qref.qgemm_via_complex("C" if conj else "T", "N", 1, 1, n, [1.0, 0, 0, 0], X, Y, [0.0] * 4,
+                                  np.zeros((1, 1, 4)))[0, 0]
+    np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+@pytest.mark.parametrize("trans", "NTCR")
+def test_qgemv_vs_complex_embedding(trans):
+    """alpha op(A) x + beta y against the complex block representation, x and
+    y strided; alpha = 0 reads neither A nor x, beta = 0 does not read y."""
+    g = W.rng(210 + "NTCR".index(trans))
+    M, N = 7, 5
+    A = W.qmatrix(g, M, N, ld=M + 1)
+    rows, cols = (M, N) if trans in "NR" else (N, M)
+    x, y = W.qvector(g, cols, 2), W.qvector(g, rows, 3)
+    al, be = W.quaternion(g), W.quaternion(g)
+    got = oracle.qgemv(trans, M, N, al, A, M + 1, x, 2, be, y, 3)
+    X = np.ascontiguousarray(x[::2][:cols][None])
+    Yl = y[::3][:rows][:, None, :]
+    want = qref.qgemm_via_complex(trans, "N", rows, 1, cols, al, A, X, be, Yl)[:, 0]
+    np.testing.assert_allclose(got[::3][:rows], want, atol=1e-13)
+    assert np.isnan(got[1::3]).all()
+    z = oracle.qgemv(trans, M, N, np.zeros(4), np.full_like(A, np.nan), M + 1, np.full_like(x, np.nan), 2, be, y, 3)
+    np.testing.assert_allclose(z[::3][:rows], [qref.bf_mul(be, v) for v in y[::3][:rows]], atol=1e-15)
+    b0 = oracle.qgemv(trans, M, N, al, A, M + 1, x, 2, np.zeros(4), np.full_like(y, np.nan), 3)
+    assert np.isfinite(b0[::3][:rows]).all()
+
+
 # ---------------------------------------------------------------- gradient
 def _loss(opA, opB, M, N, K, al, A, lda, B, ldb, G, be, C0):
     out = oracle.qgemm(opA, opB, M, N, K, al, A, lda, B, ldb, be, C0, M)
@@ -692,6 +743,9 @@ MUTANTS = [
     ("else           oracle_hamilton(B + 4 * (mu + ka * ldb), opt + 4 * (ka + nu * n), t);",
      "else           oracle_hamilton(opt + 4 * (ka + nu * n), B + 4 * (mu + ka * ldb), t);"),  # right side commuted
     ("oracle_hamilton(alpha, acc, C + 4 * (mu + nu * ldc));", "oracle_hamilton(acc, alpha, C + 4 * (mu + nu * ldc));"),  # trmm alpha right
+    ("oracle_hamilton(opa + 4 * (r + c * rows), x + 4 * c * incx, t);",
+     "oracle_hamilton(x + 4 * c * incx, opa + 4 * (r + c * rows), t);"),   # gemv commuted
+    ("if (conj) conj_q(x + 4 * i * incx, xi);", "if (conj) conj_q(y + 4 * i * incy, xi);"),   # dotc conjugates y
     ("Q[4 * (r + c * sr) + k] = X[type * (r + c * ldx) + k];",
      "Q[4 * (r + c * sr) + (type == 2 ? 2 * k : k)] = X[type * (r + c * ldx) + k];"),  # complex into e0, e2
 ]
@@ -753,6 +807,25 @@ def _mutant_pins_fail(so):
     b0, b1 = _qcomplex_pair(qref.apply_op("N", m["B"], 5, 4))
     c0, c1 = Y @ b0, Y @ b1
     if not np.allclose(qref.logical(out, 3, 4), np.stack([c0.real, c0.imag, c1.real, c1.imag], axis=-1)):
+        return True
+    L.oracle_qgemv.argtypes = [ctypes.c_int, i64, i64, dp, dp, i64, dp, i64, dp, dp, i64]
+    L.oracle_qdot.argtypes = [ctypes.c_int, i64, dp, i64, dp, i64, dp]
+    g = W.rng(11)
+    A = W.qmatrix(g, 4, 3)
+    x, y = W.qvector(g, 3), W.qvector(g, 4)
+    al = np.array([1.0, 0, 0, 0])
+    yo = y.copy()
+    L.oracle_qgemv(0, 4, 3, P(al), P(A), 4, P(x), 1, P(np.zeros(4)), P(yo), 1)
+    want = qref.qgemm_via_complex("N", "N", 4, 1, 3, al, A, np.ascontiguousarray(x[None]), [0.0] * 4,
+                                  np.zeros((4, 1, 4)))[:, 0]
+    if not np.allclose(yo, want):
+        return True
+    r = np.zeros(4)
+    x2 = np.ascontiguousarray(y[:3])
+    L.oracle_qdot(1, 3, P(x), 1, P(x2), 1, P(r))
+    want = qref.qgemm_via_complex("C", "N", 1, 1, 3, al, np.ascontiguousarray(x[None]),
+                                  np.ascontiguousarray(x2[None]), [0.0] * 4, np.zeros((1, 1, 4)))[0, 0]
+    if not np.allclose(r, want):
         return True
     return False
 

@@ -132,6 +132,16 @@ def mixed_problem(seed, typeA, typeB, M, N, K, opA="N", opB="N", dist="uniform",
                 beta=quaternion(g), A=A, lda=lda, B=B, ldb=ldb, C=C, ldc=ldc)
 
 
+def qvector(g, n, inc=1, dist="uniform", dtype=np.float64):
+    """n quaternions strided by inc elements, storage shape ((n-1) inc + 1, 4);
+    the slots between them hold NaN (never read)."""
+    length = (n - 1) * inc + 1 if n > 0 else 1
+    out = np.full((length, 4), np.nan, dtype=dtype)
+    v = g.uniform(-1.0, 1.0, (n, 4)) if dist == "uniform" else g.standard_normal((n, 4))
+    out[::inc][:n] = v.astype(dtype)
+    return out
+
+
 SWEEP_SIZES = (1024, 2048, 4096, 8192)
 OP_PAIRS = tuple((a, b) for a in "NTC" for b in "NTC")
 
