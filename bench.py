@@ -18,7 +18,7 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    rate and its error against the oracle on sampled outputs.
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
-    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed    one part, no CPU baseline
+    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed|blas12    one part, no CPU baseline
 """
 import argparse
 import hashlib
@@ -350,6 +350,56 @@ def variant_mixed(steps, warmup):
     return out
 
 
+def variant_blas12(steps, warmup):
+    """Level-1/2 operations, HBM-bound: algorithmic bytes (each operand read
+    once, each output written once) over the HIP-event time, against the
+    8 TB/s HBM peak.  gemv 8192 x 8192 FP64 (op N and op C) and FP32 (op N),
+    axpy and dotc over 2^26 FP64 quaternions; errors against the oracle."""
+    import oracle
+    out = {}
+    g = W.rng(W.BASE_SEED + 20)
+    M = N = 8192
+    A64 = W.qmatrix(g, M, N)
+    x64, y64 = W.qvector(g, N), W.qvector(g, M)
+    al, be = W.quaternion(g), W.quaternion(g)
+    for trans, dt, name in (("N", np.float64, "fp64_gemv_8192_N"), ("C", np.float64, "fp64_gemv_8192_C"),
+                            ("N", np.float32, "fp32_gemv_8192_N")):
+        A, x, y = dev(A64.astype(dt)), dev(x64.astype(dt)), dev(y64.astype(dt))
+        y0 = y.clone()
+        _, ev = time_launches(lambda: q.qgemv(trans, M, N, al, A, M, x, 1, be, y, 1), steps, warmup)
+        y.copy_(y0)
+        q.qgemv(trans, M, N, al, A, M, x, 1, be, y, 1)
+        want = oracle.qgemv(trans, M, N, al, A64.astype(dt), M, x64.astype(dt), 1, be, y64.astype(dt), 1)
+        es = np.dtype(dt).itemsize * 4
+        nbytes = es * (M * N + N + 2 * M)
+        out[name] = {"ms": round(ev, 4), "algorithmic_gbps": round(nbytes / (ev * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(nbytes / (ev * 1e-3) / 8e12, 4),
+                     "rel_err_vs_oracle": float(f"{relfro(y.cpu().numpy(), want):.3e}")}
+        del A, x, y, y0
+    n = 1 << 26
+    xs, ys = W.qvector(g, n), W.qvector(g, n)
+    x, y = dev(xs), dev(ys)
+    y0 = y.clone()
+    _, ev = time_launches(lambda: q.qaxpy(n, al, x, 1, y, 1), steps, warmup)
+    y.copy_(y0)
+    q.qaxpy(n, al, x, 1, y, 1)
+    sl = slice(0, 1 << 16)
+    want = oracle.qaxpy(1 << 16, al, xs[sl], 1, ys[sl], 1)
+    out["fp64_axpy_2^26"] = {"ms": round(ev, 4), "algorithmic_gbps": round(96 * n / (ev * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(96 * n / (ev * 1e-3) / 8e12, 4),
+                             "rel_err_vs_oracle_first_65536": float(f"{relfro(y.cpu().numpy()[sl], want):.3e}")}
+    res = torch.empty(4, dtype=torch.float64, device="cuda")
+    work = torch.empty(q._lib.DOT_WORK_DOUBLES, dtype=torch.float64, device="cuda")
+    _, ev = time_launches(lambda: q.qdot(n, x, 1, y0, 1, conj=True, result=res, work=work), steps, warmup)
+    want = oracle.qdot(True, n, xs, 1, ys, 1)
+    out["fp64_dotc_2^26"] = {"ms": round(ev, 4), "algorithmic_gbps": round(64 * n / (ev * 1e-3) / 1e9, 1),
+                             "hbm_frac": round(64 * n / (ev * 1e-3) / 8e12, 4),
+                             "rel_err_vs_oracle": float(f"{relfro(res.cpu().numpy(), want):.3e}")}
+    del x, y, y0
+    torch.cuda.empty_cache()
+    return out
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -370,7 +420,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -385,10 +435,10 @@ def main():
         calibrate_copy()
         return
 
-    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm", "mixed"):
+    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12"):
         fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
               "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm,
-              "mixed": variant_mixed}[args.only]
+              "mixed": variant_mixed, "blas12": variant_blas12}[args.only]
         print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
@@ -439,7 +489,7 @@ def main():
         variants = {}
         for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
                          ("scalars", variant_scalars), ("herk", variant_herk), ("trmm", variant_trmm),
-                         ("mixed", variant_mixed)):
+                         ("mixed", variant_mixed), ("blas12", variant_blas12)):
             log(f"[bench] variant {name}")
             variants.update(fn(args.steps, args.warmup))
             torch.cuda.empty_cache()

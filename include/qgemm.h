@@ -248,6 +248,55 @@ qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, 
                              double *C, int64_t ldc, void *stream);
 
 /*
+ * Level-1/2 operations (the quaternion BLAS-1/2 subset the paper's library
+ * provides, Sec. 5), BLAS conventions: vectors are n quaternions strided by
+ * inc >= 1 elements (4 reals each); scalars are host arrays of 4 doubles
+ * multiplying from the left; _d works on double, _s on float storage, and
+ * both accumulate in double.  These operations read O(1) flops per byte and
+ * are bound by HBM bandwidth.  Every reduction runs in a fixed order, so a
+ * result is reproducible bit for bit.  Vectors / matrices must be aligned to
+ * one quaternion (32 bytes double, 16 bytes float).
+ *
+ * qaxpy_d / qaxpy_s -- y_i <- alpha x_i + y_i, i < n.  alpha == 0 or n == 0:
+ *   y untouched.  x and y may be the same vector (same pointer and inc) but
+ *   must not overlap otherwise.
+ *   Arguments: 1 n, 2 alpha, 3 x, 4 incx, 5 y, 6 incy, then stream.
+ */
+qgemm_status_t qaxpy_d(int64_t n, const double *alpha, const double *x, int64_t incx, double *y, int64_t incy,
+                       void *stream);
+qgemm_status_t qaxpy_s(int64_t n, const double *alpha, const float *x, int64_t incx, float *y, int64_t incy,
+                       void *stream);
+
+/*
+ * qdot_d / qdot_s -- result <- sum_i x_i y_i (conj == 0) or sum_i conj(x_i) y_i
+ *   (conj == 1), written to device memory `result` (4 reals of the storage
+ *   type; n == 0 gives zero).  `work` is a device workspace of at least
+ *   QGEMM_DOT_WORK_DOUBLES doubles (partial sums), owned by the caller and
+ *   needed only when n > 0; calls that share it must not overlap.
+ *   Arguments: 1 conj, 2 n, 3 x, 4 incx, 5 y, 6 incy, 7 result, 8 work, then
+ *   stream.
+ */
+#define QGEMM_DOT_WORK_DOUBLES 4096
+qgemm_status_t qdot_d(int conj, int64_t n, const double *x, int64_t incx, const double *y, int64_t incy,
+                      double *result, double *work, void *stream);
+qgemm_status_t qdot_s(int conj, int64_t n, const float *x, int64_t incx, const float *y, int64_t incy,
+                      float *result, double *work, void *stream);
+
+/*
+ * qgemv_d / qgemv_s -- y <- alpha op(A) x + beta y with A stored M x N
+ *   (lda >= max(1, M)): op N or R gives x of N and y of M elements, op T or C
+ *   x of M and y of N elements.  Quick returns (y untouched): M == 0, N == 0,
+ *   or alpha == 0 with beta == 1.  beta == 0: y not read; alpha == 0: A and x
+ *   not read.  y must not overlap A or x.
+ *   Arguments: 1 trans, 2 M, 3 N, 4 alpha, 5 A, 6 lda, 7 x, 8 incx, 9 beta,
+ *   10 y, 11 incy, then stream.
+ */
+qgemm_status_t qgemv_d(int trans, int64_t M, int64_t N, const double *alpha, const double *A, int64_t lda,
+                       const double *x, int64_t incx, const double *beta, double *y, int64_t incy, void *stream);
+qgemm_status_t qgemv_s(int trans, int64_t M, int64_t N, const double *alpha, const float *A, int64_t lda,
+                       const float *x, int64_t incx, const double *beta, float *y, int64_t incy, void *stream);
+
+/*
  * Grouped (batched) FP32 quaternion GEMM: many independent problems
  *   C_i <- alpha op(A_i) op(B_i) + beta C_i,  i = 0..count-1,
  * with common ops, scalars and split, run as ONE persistent kernel launch

@@ -10,7 +10,8 @@ contiguous tensor of shape (cols, ld, 4): column-major, four interleaved
 components (q0, q1, q2, q3) per element.
 """
 from ._lib import (QGemmError, GroupedPlan, TILE_CLASSES, lib, qgemm_d, qgemm_s, qgemm_ex,  # noqa: F401
-                   qherk, qtrmm, qgemm_mixed, qgemm_backward, exported_symbols)
+                   qherk, qtrmm, qgemm_mixed, qaxpy, qdot, qgemv, qgemm_backward,
+                   exported_symbols)
 from .autograd import QGemmFn, QLinear, qgemm  # noqa: F401
 
 

@@ -56,6 +56,12 @@ _SIGNATURES = {
     "qtrmm_s": ([_int, _int, _int, _int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp], _int),
     "qgemm_mixed_d": ([_int, _int, _int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp],
                       _int),
+    "qaxpy_d": ([_i64, _dp, _vp, _i64, _vp, _i64, _vp], _int),
+    "qaxpy_s": ([_i64, _dp, _vp, _i64, _vp, _i64, _vp], _int),
+    "qdot_d": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp], _int),
+    "qdot_s": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp], _int),
+    "qgemv_d": ([_int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
+    "qgemv_s": ([_int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
                                    _int, _int], _int),
     "qgemm_batched_run": ([_vp, _vp], _int),
@@ -354,3 +360,65 @@ def qgemm_mixed(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C,
     rc = lib().qgemm_mixed_d(TYPES[typeA], TYPES[typeB], OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb,
                              pb, _ptr(C), ldc, _stream(stream))
     _raise(rc, "qgemm_mixed_d")
+
+
+DOT_WORK_DOUBLES = 4096      # QGEMM_DOT_WORK_DOUBLES of include/qgemm.h
+
+
+def _check_vector(t, n, inc, dtype, name):
+    """n quaternions strided by inc need ((n-1) inc + 1) * 4 reals."""
+    if n == 0:
+        return
+    _check_storage(t, 1, n, inc, dtype, name)
+
+
+def _suffix(dtype):
+    if dtype == torch.float64:
+        return "d"
+    if dtype == torch.float32:
+        return "s"
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def qaxpy(n, alpha, x, incx, y, incy, stream=None):
+    """y_i <- alpha x_i + y_i over n quaternions (C-ABI qaxpy_d / qaxpy_s)."""
+    _check_vector(x, n, incx, y.dtype, "x")
+    _check_vector(y, n, incy, y.dtype, "y")
+    pa, _ka = _q4(alpha)
+    name = "qaxpy_" + _suffix(y.dtype)
+    _raise(getattr(lib(), name)(n, pa, _ptr(x), incx, _ptr(y), incy, _stream(stream)), name)
+
+
+def qdot(n, x, incx, y, incy, conj=False, result=None, work=None, stream=None):
+    """sum x_i y_i (conj: sum conj(x_i) y_i) into the device tensor `result`
+    (4 reals, allocated when None) through a device workspace `work` of
+    DOT_WORK_DOUBLES doubles (allocated when None).  Returns `result`."""
+    dtype = x.dtype if x is not None else torch.float64
+    _check_vector(x, n, incx, dtype, "x")
+    _check_vector(y, n, incy, dtype, "y")
+    if result is None:
+        result = torch.empty(4, dtype=dtype, device="cuda")
+    if work is None and n > 0:
+        work = torch.empty(DOT_WORK_DOUBLES, dtype=torch.float64, device="cuda")
+    if work is not None and (work.dtype != torch.float64 or work.numel() < DOT_WORK_DOUBLES):
+        raise ValueError(f"work must hold {DOT_WORK_DOUBLES} float64 values")
+    name = "qdot_" + _suffix(dtype)
+    _raise(getattr(lib(), name)(int(bool(conj)), n, _ptr(x), incx, _ptr(y), incy, _ptr(result), _ptr(work),
+                                _stream(stream)), name)
+    return result
+
+
+def qgemv(trans, M, N, alpha, A, lda, x, incx, beta, y, incy, stream=None):
+    """y <- alpha op(A) x + beta y, A stored M x N (C-ABI qgemv_d / qgemv_s)."""
+    dtype = y.dtype
+    tr = trans in ("T", "C")
+    nx, ny = (M, N) if tr else (N, M)
+    if M and N:
+        _check_storage(A, M, N, lda, dtype, "A")
+        _check_vector(x, nx, incx, dtype, "x")
+        _check_vector(y, ny, incy, dtype, "y")
+    pa, _ka = _q4(alpha)
+    pb, _kb = _q4(beta)
+    name = "qgemv_" + _suffix(dtype)
+    _raise(getattr(lib(), name)(OPS[trans], M, N, pa, _ptr(A), lda, _ptr(x), incx, pb, _ptr(y), incy,
+                                _stream(stream)), name)

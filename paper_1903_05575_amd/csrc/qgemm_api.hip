@@ -25,6 +25,7 @@ bool op_conjugates(int op) { return op == QGEMM_OP_C || op == QGEMM_OP_R; }
 bool is_zero4(const double *q) { return q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0 && q[3] == 0.0; }
 
 constexpr int64_t kMaxDim = 0x7fffffff;
+static_assert(QGEMM_DOT_WORK_DOUBLES >= 4 * qg::kDotParts, "dot workspace holds every partial sum");
 
 // Validate a GEMM call.  Argument numbering follows the public signatures:
 // 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 alpha, 7 A, 8 lda, 9 B, 10 ldb, 11 beta,
@@ -365,6 +366,91 @@ qgemm_status_t trmm_impl(int side, int uplo, int trans, int diag, int64_t M, int
     return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
 }
 
+// Bytes spanned by n strided quaternions of `qbytes` bytes each.
+bool vec_overlap(const void *X, int64_t nx, int64_t incx, const void *Y, int64_t ny, int64_t incy, int64_t qbytes)
+{
+    return ranges_overlap(X, incx, 1, nx, Y, incy, 1, ny, qbytes);
+}
+
+template <typename T>
+qgemm_status_t axpy_impl(int64_t n, const double *alpha, const T *x, int64_t incx, T *y, int64_t incy,
+                         hipStream_t stream)
+{
+    constexpr uintptr_t align = 4 * sizeof(T);
+    g_bad_arg = 0;
+    if (n < 0) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (incx < 1) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (incy < 1) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (n == 0 || is_zero4(alpha)) return QGEMM_OK;
+    if (!x) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (!y) return fail(QGEMM_ERR_INVALID_ARG, 5);
+    if (reinterpret_cast<uintptr_t>(x) % align) return fail(QGEMM_ERR_MISALIGNED, 3);
+    if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 5);
+    if (!(x == y && incx == incy) && vec_overlap(x, n, incx, y, n, incy, 4 * sizeof(T)))
+        return fail(QGEMM_ERR_INVALID_ARG, 5);
+    return qg::launch_qaxpy<T>(n, alpha, x, incx, y, incy, stream) == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
+}
+
+template <typename T>
+qgemm_status_t dot_impl(int conj, int64_t n, const T *x, int64_t incx, const T *y, int64_t incy, T *result,
+                        double *work, hipStream_t stream)
+{
+    constexpr uintptr_t align = 4 * sizeof(T);
+    g_bad_arg = 0;
+    if (conj != 0 && conj != 1) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (n < 0) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (incx < 1) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (incy < 1) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (!result) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    if (reinterpret_cast<uintptr_t>(result) % sizeof(T)) return fail(QGEMM_ERR_MISALIGNED, 7);
+    if (n > 0) {
+        if (!x) return fail(QGEMM_ERR_INVALID_ARG, 3);
+        if (!y) return fail(QGEMM_ERR_INVALID_ARG, 5);
+        if (!work) return fail(QGEMM_ERR_INVALID_ARG, 8);
+        if (reinterpret_cast<uintptr_t>(x) % align) return fail(QGEMM_ERR_MISALIGNED, 3);
+        if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 5);
+        if (reinterpret_cast<uintptr_t>(work) % sizeof(double)) return fail(QGEMM_ERR_MISALIGNED, 8);
+    }
+    return qg::launch_qdot<T>(conj == 1, n, x, incx, y, incy, result, work, stream) == hipSuccess ? QGEMM_OK
+                                                                                                : QGEMM_ERR_HIP;
+}
+
+template <typename T>
+qgemm_status_t gemv_impl(int trans, int64_t M, int64_t N, const double *alpha, const T *A, int64_t lda, const T *x,
+                         int64_t incx, const double *beta, T *y, int64_t incy, hipStream_t stream)
+{
+    constexpr uintptr_t align = 4 * sizeof(T);
+    g_bad_arg = 0;
+    if (!valid_op(trans)) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (M < 0) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (N < 0) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (M > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 2);
+    if (N > kMaxDim) return fail(QGEMM_ERR_UNSUPPORTED, 3);
+    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (lda < (M > 1 ? M : 1)) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (incx < 1) return fail(QGEMM_ERR_INVALID_ARG, 8);
+    if (!beta) return fail(QGEMM_ERR_INVALID_ARG, 9);
+    if (incy < 1) return fail(QGEMM_ERR_INVALID_ARG, 11);
+    if (M == 0 || N == 0) return QGEMM_OK;
+    const bool alpha_zero = is_zero4(alpha);
+    if (alpha_zero && beta[0] == 1.0 && beta[1] == 0.0 && beta[2] == 0.0 && beta[3] == 0.0) return QGEMM_OK;
+    const bool tr = trans == QGEMM_OP_T || trans == QGEMM_OP_C;
+    const int64_t nx = tr ? M : N, ny = tr ? N : M;
+    if (!alpha_zero && !A) return fail(QGEMM_ERR_INVALID_ARG, 5);
+    if (!alpha_zero && !x) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    if (!y) return fail(QGEMM_ERR_INVALID_ARG, 10);
+    if (!alpha_zero && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 5);
+    if (!alpha_zero && (reinterpret_cast<uintptr_t>(x) % align)) return fail(QGEMM_ERR_MISALIGNED, 7);
+    if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 10);
+    if (!alpha_zero && (vec_overlap(x, nx, incx, y, ny, incy, 4 * sizeof(T)) ||
+                        ranges_overlap(A, lda, M, N, y, incy, 1, ny, 4 * sizeof(T))))
+        return fail(QGEMM_ERR_INVALID_ARG, 10);
+    return qg::launch_qgemv<T>(trans, (int)M, (int)N, alpha, A, lda, x, incx, beta, y, incy, stream) == hipSuccess
+               ? QGEMM_OK
+               : QGEMM_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -518,6 +604,42 @@ qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, 
     if (!qg::mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc)) return fail(QGEMM_ERR_UNSUPPORTED, right ? 12 : 10);
     if (qg::launch_qgemm_mixed_f64(d, static_cast<hipStream_t>(stream)) != hipSuccess) return QGEMM_ERR_HIP;
     return QGEMM_OK;
+}
+
+qgemm_status_t qaxpy_d(int64_t n, const double *alpha, const double *x, int64_t incx, double *y, int64_t incy,
+                       void *stream)
+{
+    return axpy_impl<double>(n, alpha, x, incx, y, incy, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qaxpy_s(int64_t n, const double *alpha, const float *x, int64_t incx, float *y, int64_t incy,
+                       void *stream)
+{
+    return axpy_impl<float>(n, alpha, x, incx, y, incy, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qdot_d(int conj, int64_t n, const double *x, int64_t incx, const double *y, int64_t incy,
+                      double *result, double *work, void *stream)
+{
+    return dot_impl<double>(conj, n, x, incx, y, incy, result, work, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qdot_s(int conj, int64_t n, const float *x, int64_t incx, const float *y, int64_t incy,
+                      float *result, double *work, void *stream)
+{
+    return dot_impl<float>(conj, n, x, incx, y, incy, result, work, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qgemv_d(int trans, int64_t M, int64_t N, const double *alpha, const double *A, int64_t lda,
+                       const double *x, int64_t incx, const double *beta, double *y, int64_t incy, void *stream)
+{
+    return gemv_impl<double>(trans, M, N, alpha, A, lda, x, incx, beta, y, incy, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qgemv_s(int trans, int64_t M, int64_t N, const double *alpha, const float *A, int64_t lda,
+                       const float *x, int64_t incx, const double *beta, float *y, int64_t incy, void *stream)
+{
+    return gemv_impl<float>(trans, M, N, alpha, A, lda, x, incx, beta, y, incy, static_cast<hipStream_t>(stream));
 }
 
 qgemm_status_t qgemm_backward_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,

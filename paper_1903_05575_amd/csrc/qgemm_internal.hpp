@@ -90,6 +90,19 @@ struct MixedDesc {
 bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc);
 hipError_t launch_qgemm_mixed_f64(const MixedDesc &d, hipStream_t stream);
 
+// Level-1/2 launches (qblas_l12.hip).  The dot product uses at most
+// kDotParts partial sums of 4 doubles in the caller's workspace.
+constexpr int kDotParts = 1024;
+template <typename T>
+hipError_t launch_qaxpy(int64_t n, const double *alpha, const T *x, int64_t incx, T *y, int64_t incy,
+                        hipStream_t stream);
+template <typename T>
+hipError_t launch_qdot(bool conj, int64_t n, const T *x, int64_t incx, const T *y, int64_t incy, T *result,
+                       double *work, hipStream_t stream);
+template <typename T>
+hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A, int64_t lda, const T *x,
+                        int64_t incx, const double *beta, T *y, int64_t incy, hipStream_t stream);
+
 // Grouped (batched) split-BF16 plans; see qgemm_grouped.hip.
 struct GroupedPlan;
 constexpr int kGroupedClasses = 5;

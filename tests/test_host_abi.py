@@ -221,3 +221,52 @@ def test_validation_mixed(L, kw, arg, status):
 def test_mixed_real_alignment_is_one_double(L):
     # a real B at an 8-byte offset is aligned; the call then fails later on the misaligned quaternion C
     assert call_mixed(L, B=FAKE_B + 8, C=FAKE_C + 8) == 2 and L.qgemm_last_invalid_arg() == 14
+
+
+def test_validation_level12(L):
+    """qaxpy_*: 1 n, 2 alpha, 3 x, 4 incx, 5 y, 6 incy.  qdot_*: 1 conj, 2 n,
+    3 x, 4 incx, 5 y, 6 incy, 7 result, 8 work.  qgemv_*: 1 trans, 2 M, 3 N,
+    4 alpha, 5 A, 6 lda, 7 x, 8 incx, 9 beta, 10 y, 11 incy."""
+    def ax(*a):
+        return L.qaxpy_d(*a, None), L.qgemm_last_invalid_arg()
+    assert ax(-1, ONE, FAKE, 1, FAKE_B, 1) == (1, 1)
+    assert ax(4, None, FAKE, 1, FAKE_B, 1) == (1, 2)
+    assert ax(4, ONE, FAKE, 0, FAKE_B, 1) == (1, 4)
+    assert ax(4, ONE, FAKE, 1, FAKE_B, -1) == (1, 6)
+    assert ax(4, ONE, None, 1, FAKE_B, 1) == (1, 3)
+    assert ax(4, ONE, FAKE, 1, None, 1) == (1, 5)
+    assert ax(4, ONE, FAKE + 16, 1, FAKE_B, 1) == (2, 3)
+    assert ax(4, ONE, FAKE, 2, FAKE + 32, 2) == (1, 5)            # interleaved x and y overlap
+    assert ax(0, ONE, None, 1, None, 1) == (0, 0)                 # nothing to do
+    assert ax(4, q4(0, 0, 0, 0), None, 1, None, 1) == (0, 0)      # alpha = 0: y untouched
+    assert L.qaxpy_s(4, ONE, FAKE + 8, 1, FAKE_B, 1, None) == 2 and L.qgemm_last_invalid_arg() == 3
+
+    def dot(*a):
+        return L.qdot_d(*a, None), L.qgemm_last_invalid_arg()
+    assert dot(2, 4, FAKE, 1, FAKE_B, 1, FAKE_C, 0x40000) == (1, 1)
+    assert dot(0, -4, FAKE, 1, FAKE_B, 1, FAKE_C, 0x40000) == (1, 2)
+    assert dot(0, 4, FAKE, 0, FAKE_B, 1, FAKE_C, 0x40000) == (1, 4)
+    assert dot(0, 4, FAKE, 1, FAKE_B, 0, FAKE_C, 0x40000) == (1, 6)
+    assert dot(0, 4, FAKE, 1, FAKE_B, 1, None, 0x40000) == (1, 7)
+    assert dot(0, 4, FAKE, 1, FAKE_B, 1, FAKE_C, None) == (1, 8)
+    assert dot(0, 4, FAKE + 8, 1, FAKE_B, 1, FAKE_C, 0x40000) == (2, 3)
+    assert dot(0, 4, FAKE, 1, FAKE_B, 1, FAKE_C + 4, 0x40000) == (2, 7)
+
+    def gv(trans=0, M=4, N=4, alpha=ONE, A=FAKE, lda=4, x=FAKE_B, incx=1, beta=ONE, y=FAKE_C, incy=1):
+        return L.qgemv_d(trans, M, N, alpha, A, lda, x, incx, beta, y, incy, None), L.qgemm_last_invalid_arg()
+    assert gv(trans=4) == (1, 1)
+    assert gv(M=-1) == (1, 2)
+    assert gv(N=-1) == (1, 3)
+    assert gv(alpha=None) == (1, 4)
+    assert gv(lda=3) == (1, 6)
+    assert gv(incx=0) == (1, 8)
+    assert gv(beta=None) == (1, 9)
+    assert gv(incy=0) == (1, 11)
+    assert gv(A=None) == (1, 5)
+    assert gv(x=None) == (1, 7)
+    assert gv(y=None) == (1, 10)
+    assert gv(y=FAKE_B) == (1, 10)                                # y aliases x
+    assert gv(y=FAKE + 64) == (1, 10)                             # y inside A
+    assert gv(A=FAKE + 8) == (2, 5)
+    assert gv(M=0, A=None, x=None, y=None) == (0, 0)
+    assert gv(alpha=q4(0, 0, 0, 0), A=None, x=None, y=None) == (0, 0)   # alpha = 0, beta = 1
