@@ -14,11 +14,16 @@ multiply-add, 2 flops each).  Beside it the line carries:
   cpu_baseline  -- the CPU oracle timed on this host on a bounded column sample;
   variants      -- the split-BF16 FP32 path, the grouped batched launch, the
                    linear-layer forward + backward, the general scalar
-                   placement and the Hermitian rank-k update, each with its own
-                   rate and its error against the oracle on sampled outputs.
+                   placement, the Hermitian rank-k update, the triangular
+                   multiply, the mixed-type products, the level-1/2
+                   operations and the one-GPU row shard, each with its own
+                   rate and its error against the oracle on sampled outputs,
+                   plus vendor context (rocBLAS ZGEMM / DGEMM on embeddings).
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
-    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed|blas12    one part, no CPU baseline
+    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed|blas12|shard|context
+                                                   one part, no CPU baseline
+    python bench.py --sweep                        FP64 sizes 1024..8192 x op pairs, one line each
 """
 import argparse
 import hashlib
@@ -104,8 +109,15 @@ def cpu_baseline(p, ncols):
     oracle.qgemm(p["opA"], p["opB"], M, ncols, K, p["alpha"], p["A"], p["lda"], B, p["ldb"],
                  p["beta"], C, p["ldc"])
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": round(q.flops(M, ncols, K) / dt / 1e12, 6), "unit": "TFLOP/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)),
             "sample": f"op {p['opA']}/{p['opB']}, M=K={M}, first {ncols} of {p['N']} columns of C "
                       f"({q.flops(M, ncols, K):.3g} flops in {dt:.1f} s)"}
 
@@ -354,8 +366,11 @@ def variant_blas12(steps, warmup):
     """Level-1/2 operations, HBM-bound: algorithmic bytes (each operand read
     once, each output written once) over the HIP-event time, against the
     8 TB/s HBM peak.  gemv 8192 x 8192 FP64 (op N and op C) and FP32 (op N),
-    axpy and dotc over 2^26 FP64 quaternions; errors against the oracle."""
+    axpy and dotc over 2^26 FP64 quaternions; errors against the oracle.
+    These calls take well under a millisecond, so each is timed over ten
+    times the requested number of steps."""
     import oracle
+    steps = 10 * steps
     out = {}
     g = W.rng(W.BASE_SEED + 20)
     M = N = 8192
@@ -395,9 +410,96 @@ def variant_blas12(steps, warmup):
     out["fp64_dotc_2^26"] = {"ms": round(ev, 4), "algorithmic_gbps": round(64 * n / (ev * 1e-3) / 1e9, 1),
                              "hbm_frac": round(64 * n / (ev * 1e-3) / 8e12, 4),
                              "rel_err_vs_oracle": float(f"{relfro(res.cpu().numpy(), want):.3e}")}
+    # achievable-bandwidth reference: a plain device copy of the same 2^26 quaternions
+    _, ev = time_launches(lambda: y0.copy_(x), steps, warmup)
+    out["reference_device_copy_2^26"] = {"ms": round(ev, 4), "gbps": round(64 * n / (ev * 1e-3) / 1e9, 1),
+                                         "hbm_frac": round(64 * n / (ev * 1e-3) / 8e12, 4)}
     del x, y, y0
     torch.cuda.empty_cache()
     return out
+
+
+def variant_shard(steps, warmup):
+    """One GPU's share of an 8-way row split of the 8192^3 FP64 GEMM:
+    M = 1024 rows of op(A) and C, N = K = 8192 (op N/N)."""
+    M, N, K = 1024, 8192, 8192
+    p = W.gemm_problem(W.BASE_SEED + 30, M, N, K, "N", "N")
+    A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
+    _, ev = time_launches(lambda: q.qgemm_d("N", "N", M, N, K, p["alpha"], A, M, B, K, p["beta"], C, M), steps,
+                          warmup)
+    fl = q.flops(M, N, K)
+    return {"fp64_row_shard_1024x8192x8192": {"ms": round(ev, 3), "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
+                                              "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4)}}
+
+
+def variant_context(steps, warmup):
+    """Vendor context for the 8192^3 FP64 product on the same data (not a
+    target): rocBLAS ZGEMM through torch.matmul on the complex block
+    representation [[A0 + i A1, A2 + i A3], [-conj(A2 + i A3), conj(A0 + i A1)]]
+    (2M x 2K times 2K x 2N, 64 MNK real flops), and rocBLAS DGEMM on the real
+    left-multiplication embedding L(op A) (4M x 4K) times B read as a 4K x N
+    real matrix (32 MNK flops, the same contraction this library runs)."""
+    import oracle
+    n = 8192
+    p = W.gemm_sweep(n, "N", "N")
+    one, zero = np.array([1.0, 0, 0, 0]), np.zeros(4)
+    out = {}
+    A = dev(p["A"])                       # storage (K, M, 4): A[k, m, c]
+    B = dev(p["B"])                       # storage (N, K, 4)
+    with torch.no_grad():
+        def cblock(S):                    # logical (rows, cols) from storage (cols, rows, 4)
+            z0 = torch.complex(S[..., 0], S[..., 1]).T
+            z1 = torch.complex(S[..., 2], S[..., 3]).T
+            return torch.cat([torch.cat([z0, z1], 1), torch.cat([-z1.conj(), z0.conj()], 1)], 0).contiguous()
+        Ac, Bc = cblock(A), cblock(B)
+        _, ev = time_launches(lambda: torch.matmul(Ac, Bc), steps, warmup)
+        Cc = torch.matmul(Ac, Bc)
+        rows, cols = np.arange(0, n, n // 16), np.arange(3, n, n // 16)
+        want = oracle.qgemm_entries("N", "N", n, one, p["A"], p["B"], zero, p["C"], rows, cols)   # (cols, rows, 4)
+        top0 = Cc[:n, :n][rows][:, cols].cpu().numpy().T
+        top1 = Cc[:n, n:][rows][:, cols].cpu().numpy().T
+        got = np.stack([top0.real, top0.imag, top1.real, top1.imag], -1)
+        out["context_rocblas_zgemm_block_embedding_8192"] = {
+            "ms": round(ev, 3), "tflops_zgemm_counted": round(64 * n ** 3 / (ev * 1e-3) / 1e12, 2),
+            "tflops_quaternion_effective": round(32 * n ** 3 / (ev * 1e-3) / 1e12, 2),
+            "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}
+        del Ac, Bc, Cc
+        torch.cuda.empty_cache()
+        # L(a)[r][c] = sign(r, c) a[r ^ c], rows 4 mu + r, columns 4 k + c
+        sign = torch.tensor([[1, -1, -1, -1], [1, 1, -1, 1], [1, 1, 1, -1], [1, -1, 1, 1]], dtype=torch.float64,
+                            device="cuda")
+        idx = torch.tensor([[r ^ c for c in range(4)] for r in range(4)], device="cuda")
+        Al = A.permute(1, 0, 2)           # (M, K, 4)
+        AL = (Al[:, :, idx] * sign).permute(0, 2, 1, 3).reshape(4 * n, 4 * n).contiguous()   # (M, r, K, c)
+        Br = B.reshape(n, 4 * n).T.contiguous()                                           # (4K, N)
+        del Al
+        _, ev = time_launches(lambda: torch.matmul(AL, Br), steps, warmup)
+        Cr = torch.matmul(AL, Br).reshape(n, 4, n)                                       # (M, r, N)
+        got = Cr[rows][:, :, cols].permute(2, 0, 1).cpu().numpy()                         # (cols, rows, 4)
+        out["context_rocblas_dgemm_L_embedding_8192"] = {
+            "ms": round(ev, 3), "tflops_effective": round(32 * n ** 3 / (ev * 1e-3) / 1e12, 2),
+            "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}
+        del AL, Br, Cr
+    del A, B
+    torch.cuda.empty_cache()
+    return out
+
+
+def sweep(steps, warmup):
+    """FP64 qgemm_d over M = N = K in 1024..8192 and every op pair of N, T, C:
+    one JSON line per case (event time per launch and effective TFLOP/s)."""
+    for n in W.SWEEP_SIZES:
+        for opA, opB in W.OP_PAIRS:
+            p = W.gemm_sweep(n, opA, opB)
+            A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
+            _, ev = time_launches(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
+                                                    p["beta"], C, p["ldc"]), steps, warmup)
+            fl = q.flops(n, n, n)
+            print(json.dumps({"sweep": f"{n} {opA}/{opB}", "ms": round(ev, 3),
+                              "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
+                              "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4)}), flush=True)
+            del A, B, C
+            torch.cuda.empty_cache()
 
 
 def calibrate_copy():
@@ -420,7 +522,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12"],
+    ap.add_argument("--sweep", action="store_true", help="time the FP64 size x op-pair sweep, one line per case")
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12", "shard",
+                                       "context"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -434,11 +538,15 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.sweep:
+        sweep(args.steps, args.warmup)
+        return
 
-    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12"):
+    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12", "shard", "context"):
         fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
               "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm,
-              "mixed": variant_mixed, "blas12": variant_blas12}[args.only]
+              "mixed": variant_mixed, "blas12": variant_blas12, "shard": variant_shard,
+              "context": variant_context}[args.only]
         print(json.dumps(fn(args.steps, args.warmup)), flush=True)
         return
 
@@ -489,7 +597,8 @@ def main():
         variants = {}
         for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
                          ("scalars", variant_scalars), ("herk", variant_herk), ("trmm", variant_trmm),
-                         ("mixed", variant_mixed), ("blas12", variant_blas12)):
+                         ("mixed", variant_mixed), ("blas12", variant_blas12), ("shard", variant_shard),
+                         ("context", variant_context)):
             log(f"[bench] variant {name}")
             variants.update(fn(args.steps, args.warmup))
             torch.cuda.empty_cache()

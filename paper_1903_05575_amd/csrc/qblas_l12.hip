@@ -51,12 +51,29 @@ struct Scalars {
     double beta[4];
 };
 
-// y_i <- alpha x_i + y_i
+// y_i <- alpha x_i + y_i; each thread takes elements i and i + stride per
+// iteration, so four loads are in flight before the first store
 template <typename T>
 __global__ __launch_bounds__(NT) void qaxpy_kernel(int64_t n, Scalars s, const T *x, int64_t incx, T *y, int64_t incy)
 {
     const int64_t stride = (int64_t)gridDim.x * NT;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+    int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    for (; i + stride < n; i += 2 * stride) {
+        double xv[2][4], yv[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            load_q(x + 4 * (i + u * stride) * incx, xv[u]);
+            load_q(y + 4 * (i + u * stride) * incy, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            double t[4];
+            qmul(s.alpha, xv[u], t);
+            t[0] += yv[u][0]; t[1] += yv[u][1]; t[2] += yv[u][2]; t[3] += yv[u][3];
+            store_q(y + 4 * (i + u * stride) * incy, t);
+        }
+    }
+    if (i < n) {
         double xv[4], yv[4], t[4];
         load_q(x + 4 * i * incx, xv);
         load_q(y + 4 * i * incy, yv);
@@ -82,7 +99,8 @@ __device__ __forceinline__ void block_sum4(double v[4], double (*red)[4])
     v[0] = red[0][0]; v[1] = red[0][1]; v[2] = red[0][2]; v[3] = red[0][3];
 }
 
-// dot pass 1: block b sums x_i y_i (conj(x_i) y_i) over i = b NT + t + k gridDim NT into work[4b..4b+3]
+// dot pass 1: block b sums x_i y_i (conj(x_i) y_i) over i = b NT + t + k gridDim NT into
+// work[4b..4b+3]; the per-thread order is fixed by n and the grid, so the result is reproducible
 template <typename T, bool CONJ>
 __global__ __launch_bounds__(NT) void qdot_partial_kernel(int64_t n, const T *x, int64_t incx, const T *y,
                                                           int64_t incy, double *work)
@@ -90,7 +108,23 @@ __global__ __launch_bounds__(NT) void qdot_partial_kernel(int64_t n, const T *x,
     __shared__ double red[NT][4];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * NT;
-    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+    int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    for (; i + stride < n; i += 2 * stride) {      // two elements, four loads in flight
+        double xv[2][4], yv[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            load_q(x + 4 * (i + u * stride) * incx, xv[u]);
+            load_q(y + 4 * (i + u * stride) * incy, yv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            double t[4];
+            if (CONJ) conj_inplace(xv[u]);
+            qmul(xv[u], yv[u], t);
+            acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[3] += t[3];
+        }
+    }
+    if (i < n) {
         double xv[4], yv[4], t[4];
         load_q(x + 4 * i * incx, xv);
         load_q(y + 4 * i * incy, yv);
@@ -121,14 +155,26 @@ __global__ __launch_bounds__(NT) void qdot_final_kernel(int parts, const double 
 }
 
 // gemv, op N / R: block = GR rows x GC column groups; thread (r, g) sums
-// op(A)[mu][nu] x[nu] over nu = g, g + GC, ... of row mu = mu0 + r, then the
-// column groups are summed in order g = 0, 1, ... in LDS.
-constexpr int GR = 16, GC = NT / GR;
+// op(A)[mu][nu] x[nu] over nu = g, g + GC, ... of row mu = mu0 + r (GU
+// columns in flight), then the column groups are summed in order
+// g = 0, 1, ... in LDS.  16 rows of one column are 512 (FP64) or 256 (FP32)
+// contiguous bytes.  Measured at 8192 x 8192: 8 columns in flight is best
+// for FP64, 4 for FP32 (more threads per block or more rows per block were
+// slower for both).
+template <typename T>
+struct GemvN {
+    static constexpr int NTB = NT;
+    static constexpr int GR = 16;
+    static constexpr int GC = NTB / GR;
+    static constexpr int GU = sizeof(T) == 8 ? 8 : 4;
+};
 
 template <typename T, bool CONJ>
-__global__ __launch_bounds__(NT) void qgemv_n_kernel(int M, int N, int ncols, Scalars s, const T *A, int64_t lda,
-                                                     const T *x, int64_t incx, bool beta_zero, T *y, int64_t incy)
+__global__ __launch_bounds__(GemvN<T>::NTB) void qgemv_n_kernel(int M, int N, int ncols, Scalars s, const T *A,
+                                                                int64_t lda, const T *x, int64_t incx,
+                                                                bool beta_zero, T *y, int64_t incy)
 {
+    constexpr int GR = GemvN<T>::GR, GC = GemvN<T>::GC, GU = GemvN<T>::GU;
     __shared__ double red[GC][GR][4];
     const int r = threadIdx.x % GR, g = threadIdx.x / GR;
     const int mu = blockIdx.x * GR + r;
@@ -136,15 +182,15 @@ __global__ __launch_bounds__(NT) void qgemv_n_kernel(int M, int N, int ncols, Sc
     if (mu < M) {
         const T *Ar = A + 4 * (int64_t)mu;
         int nu = g;
-        for (; nu + 3 * GC < ncols; nu += 4 * GC) {     // four columns in flight per thread
-            double a[4][4], xv[4][4];
+        for (; nu + (GU - 1) * GC < ncols; nu += GU * GC) {     // GU columns in flight per thread
+            double a[GU][4], xv[GU][4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < GU; ++u) {
                 load_q(Ar + 4 * (int64_t)(nu + u * GC) * lda, a[u]);
                 load_q(x + 4 * (int64_t)(nu + u * GC) * incx, xv[u]);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < GU; ++u) {
                 double t[4];
                 if (CONJ) conj_inplace(a[u]);
                 qmul(a[u], xv[u], t);
@@ -180,50 +226,70 @@ __global__ __launch_bounds__(NT) void qgemv_n_kernel(int M, int N, int ncols, Sc
     }
 }
 
-// gemv, op T / C: wave w of the block computes output nu = 4 blockIdx + w,
-// the dot product of column nu of A (conjugated for op C) with x; lanes split
-// the rows and are summed by a fixed butterfly.
+// gemv, op T / C: wave w of the block computes the TC outputs
+// nu = TC (4 blockIdx + w) + j, j < TC: dot products of columns of A
+// (conjugated for op C) with x, sharing each load of x.  Lanes split the
+// rows and are summed by a fixed butterfly.
+constexpr int TC = 4;
+
 template <typename T, bool CONJ>
 __global__ __launch_bounds__(NT) void qgemv_t_kernel(int M, int N, int nrows, Scalars s, const T *A, int64_t lda,
                                                      const T *x, int64_t incx, bool beta_zero, T *y, int64_t incy)
 {
     const int lane = threadIdx.x & 63;
-    const int nu = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-    if (nu >= N) return;                       // whole wave leaves together
-    const T *Ac = A + 4 * (int64_t)nu * lda;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nu0 = TC * (blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
+    if (nu0 >= N) return;                      // whole wave leaves together
+    int ncol = N - nu0;
+    ncol = ncol < TC ? ncol : TC;
+    const T *Ac[TC];
+#pragma unroll
+    for (int j = 0; j < TC; ++j) Ac[j] = A + 4 * (int64_t)(nu0 + (j < ncol ? j : 0)) * lda;   // spare columns repeat the first
+    double acc[TC][4] = {};
     int mu = lane;
-    for (; mu + 3 * 64 < nrows; mu += 4 * 64) {
-        double a[4][4], xv[4][4];
+    for (; mu + 64 < nrows; mu += 2 * 64) {
+        double a[2][TC][4], xv[2][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            load_q(Ac + 4 * (int64_t)(mu + 64 * u), a[u]);
+        for (int u = 0; u < 2; ++u) {
             load_q(x + 4 * (int64_t)(mu + 64 * u) * incx, xv[u]);
+#pragma unroll
+            for (int j = 0; j < TC; ++j) load_q(Ac[j] + 4 * (int64_t)(mu + 64 * u), a[u][j]);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            double t[4];
-            if (CONJ) conj_inplace(a[u]);
-            qmul(a[u], xv[u], t);
-            acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[3] += t[3];
-        }
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < TC; ++j) {
+                double t[4];
+                if (CONJ) conj_inplace(a[u][j]);
+                qmul(a[u][j], xv[u], t);
+                acc[j][0] += t[0]; acc[j][1] += t[1]; acc[j][2] += t[2]; acc[j][3] += t[3];
+            }
     }
-    for (; mu < nrows; mu += 64) {
-        double a[4], xv[4], t[4];
-        load_q(Ac + 4 * (int64_t)mu, a);
+    if (mu < nrows) {
+        double xv[4];
         load_q(x + 4 * (int64_t)mu * incx, xv);
-        if (CONJ) conj_inplace(a);
-        qmul(a, xv, t);
-        acc[0] += t[0]; acc[1] += t[1]; acc[2] += t[2]; acc[3] += t[3];
+#pragma unroll
+        for (int j = 0; j < TC; ++j) {
+            double a[4], t[4];
+            load_q(Ac[j] + 4 * (int64_t)mu, a);
+            if (CONJ) conj_inplace(a);
+            qmul(a, xv, t);
+            acc[j][0] += t[0]; acc[j][1] += t[1]; acc[j][2] += t[2]; acc[j][3] += t[3];
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off);
-    if (lane == 0) {
+        for (int j = 0; j < TC; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[j][c] += __shfl_xor(acc[j][c], off);
+    if (lane < ncol) {                          // lane j writes output nu0 + j
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < TC; ++j)
+            if (j == lane) { v[0] = acc[j][0]; v[1] = acc[j][1]; v[2] = acc[j][2]; v[3] = acc[j][3]; }
         double o[4];
-        qmul(s.alpha, acc, o);
-        T *yr = y + 4 * (int64_t)nu * incy;
+        qmul(s.alpha, v, o);
+        T *yr = y + 4 * (int64_t)(nu0 + lane) * incy;
         if (!beta_zero) {
             double yv[4], u[4];
             load_q(yr, yv);
@@ -292,16 +358,17 @@ hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A
     const bool conj = trans == QGEMM_OP_C || trans == QGEMM_OP_R;
     if (trans == QGEMM_OP_N || trans == QGEMM_OP_R) {
         const int ncols = alpha_zero ? 0 : N;
-        const dim3 grid((M + GR - 1) / GR);
+        const dim3 grid((M + GemvN<T>::GR - 1) / GemvN<T>::GR);
         if (conj)
-            hipLaunchKernelGGL((qgemv_n_kernel<T, true>), grid, dim3(NT), 0, stream, M, N, ncols, s, A, lda, x, incx,
-                               beta_zero, y, incy);
+            hipLaunchKernelGGL((qgemv_n_kernel<T, true>), grid, dim3(GemvN<T>::NTB), 0, stream, M, N, ncols, s, A,
+                               lda, x, incx, beta_zero, y, incy);
         else
-            hipLaunchKernelGGL((qgemv_n_kernel<T, false>), grid, dim3(NT), 0, stream, M, N, ncols, s, A, lda, x,
-                               incx, beta_zero, y, incy);
+            hipLaunchKernelGGL((qgemv_n_kernel<T, false>), grid, dim3(GemvN<T>::NTB), 0, stream, M, N, ncols, s, A,
+                               lda, x, incx, beta_zero, y, incy);
     } else {
         const int nrows = alpha_zero ? 0 : M;
-        const dim3 grid((N + NT / 64 - 1) / (NT / 64));
+        const int per_block = TC * (NT / 64);
+        const dim3 grid((N + per_block - 1) / per_block);
         if (conj)
             hipLaunchKernelGGL((qgemv_t_kernel<T, true>), grid, dim3(NT), 0, stream, M, N, nrows, s, A, lda, x, incx,
                                beta_zero, y, incy);
