@@ -42,9 +42,15 @@
  *     (all four components) computes C <- beta * C without reading A or B.
  *     beta == 0 (all four components) never reads C, so NaN/Inf there do not
  *     propagate.
- *   - Aliasing: C must not overlap A or B.
+ *   - Aliasing: an output must not overlap any array the call reads (C vs A
+ *     and B; each gradient vs A, B, G and the other gradients).  Checked from
+ *     the address ranges the sizes and leading dimensions span:
+ *     QGEMM_ERR_INVALID_ARG with the output's argument index.
  *   - Errors are returned as status codes; nothing aborts or throws across
  *     the ABI.  QGEMM_ERR_HIP means a HIP launch error was reported.
+ *   - Threads and devices: calls from several host threads are safe; each
+ *     call runs on the calling thread's current device (set up once per
+ *     device on first use) and on the given stream, in stream order.
  */
 #ifndef QGEMM_H
 #define QGEMM_H

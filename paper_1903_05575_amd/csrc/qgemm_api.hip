@@ -25,14 +25,29 @@ bool op_conjugates(int op) { return op == QGEMM_OP_C || op == QGEMM_OP_R; }
 bool is_zero4(const double *q) { return q[0] == 0.0 && q[1] == 0.0 && q[2] == 0.0 && q[3] == 0.0; }
 
 constexpr int64_t kMaxDim = 0x7fffffff;
+
+// Whether the bytes spanned by two column-major matrices overlap: X is xrows x
+// xcols with leading dimension ldx and xbytes per element, likewise Y.  Empty
+// matrices overlap nothing.
+bool ranges_overlap(const void *X, int64_t ldx, int64_t xrows, int64_t xcols, int64_t xbytes, const void *Y,
+                    int64_t ldy, int64_t yrows, int64_t ycols, int64_t ybytes)
+{
+    if (!X || !Y || xrows <= 0 || xcols <= 0 || yrows <= 0 || ycols <= 0) return false;
+    const uintptr_t x0 = reinterpret_cast<uintptr_t>(X), y0 = reinterpret_cast<uintptr_t>(Y);
+    const uintptr_t x1 = x0 + (uintptr_t)((ldx * (xcols - 1) + xrows) * xbytes);
+    const uintptr_t y1 = y0 + (uintptr_t)((ldy * (ycols - 1) + yrows) * ybytes);
+    return x0 < y1 && y0 < x1;
+}
 static_assert(QGEMM_DOT_WORK_DOUBLES >= 4 * qg::kDotParts, "dot workspace holds every partial sum");
 
 // Validate a GEMM call.  Argument numbering follows the public signatures:
 // 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 alpha, 7 A, 8 lda, 9 B, 10 ldb, 11 beta,
-// 12 C, 13 ldc.  `align` is the byte size of one quaternion.
+// 12 C, 13 ldc.  `align` is the byte size of one element of C (and the
+// alignment asked of every operand); `ab_bytes` the byte size of one element
+// of A and B, for the check that C overlaps neither (0: the caller checks).
 qgemm_status_t validate(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
                         const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
-                        const void *C, int64_t ldc, uintptr_t align)
+                        const void *C, int64_t ldc, uintptr_t align, int64_t ab_bytes)
 {
     g_bad_arg = 0;
     if (!valid_op(opA)) return fail(QGEMM_ERR_INVALID_ARG, 1);
@@ -58,7 +73,13 @@ qgemm_status_t validate(int opA, int opB, int64_t M, int64_t N, int64_t K, const
     if (reads_ab && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 7);
     if (reads_ab && (reinterpret_cast<uintptr_t>(B) % align)) return fail(QGEMM_ERR_MISALIGNED, 9);
     if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 12);
-    // 32-bit tile grid and element offsets computed in 64 bits: nothing more to check.
+    // C is written by some tiles while others still read A and B
+    if (reads_ab && ab_bytes) {
+        const int64_t cols_a = op_transposes(opA) ? M : K, cols_b = op_transposes(opB) ? K : N;
+        if (ranges_overlap(C, ldc, M, N, (int64_t)align, A, lda, rows_a, cols_a, ab_bytes) ||
+            ranges_overlap(C, ldc, M, N, (int64_t)align, B, ldb, rows_b, cols_b, ab_bytes))
+            return fail(QGEMM_ERR_INVALID_ARG, 12);
+    }
     return QGEMM_OK;
 }
 
@@ -164,6 +185,30 @@ qgemm_status_t backward_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, 
     if (misaligned(dB)) return fail(QGEMM_ERR_MISALIGNED, 16);
     if (misaligned(dC0)) return fail(QGEMM_ERR_MISALIGNED, 18);
     {
+        // every output is written while the other gradient launch may still read the inputs
+        struct Span {
+            const void *p;
+            int64_t ld, rows, cols;
+        };
+        const int64_t cols_a = op_transposes(opA) ? M : K, cols_b = op_transposes(opB) ? K : N;
+        const Span in[3] = {{A, lda, rows_a, cols_a}, {B, ldb, rows_b, cols_b}, {G, ldg, M, N}};
+        const Span out[3] = {{need_a ? dA : nullptr, ldda, rows_a, cols_a},
+                             {need_b ? dB : nullptr, lddb, rows_b, cols_b},
+                             {need_c ? dC0 : nullptr, lddc0, M, N}};
+        const int out_arg[3] = {14, 16, 18};
+        constexpr int64_t qb = 4 * sizeof(T);
+        for (int o = 0; o < 3; ++o) {
+            for (int i = 0; i < 3; ++i)
+                if (ranges_overlap(out[o].p, out[o].ld, out[o].rows, out[o].cols, qb, in[i].p, in[i].ld, in[i].rows,
+                                   in[i].cols, qb))
+                    return fail(QGEMM_ERR_INVALID_ARG, out_arg[o]);
+            for (int j = 0; j < o; ++j)
+                if (ranges_overlap(out[o].p, out[o].ld, out[o].rows, out[o].cols, qb, out[j].p, out[j].ld,
+                                   out[j].rows, out[j].cols, qb))
+                    return fail(QGEMM_ERR_INVALID_ARG, out_arg[o]);
+        }
+    }
+    {
         // the two gradient GEMMs read (G, op(B)^H) and (op(A)^H, G) through the GEMM tiles
         auto ok = [](int64_t l1, int64_t l2, bool t1, bool t2) {
             return sizeof(T) == 4 ? qg::split_ld_supported(l1, l2, t1, t2) : qg::f64_ld_supported(l1, l2, t1, t2);
@@ -224,7 +269,8 @@ qgemm_status_t ex_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, const 
     const double *bl = bL ? bL : zero, *br = bR ? bR : one;
     // the product vanishes when any alpha is zero: validate as for alpha = 0
     const bool az = is_zero4(l) || is_zero4(m) || is_zero4(r);
-    qgemm_status_t s = validate(opA, opB, M, N, K, az ? zero : l, A, lda, B, ldb, bl, C, ldc, 4 * sizeof(T));
+    qgemm_status_t s = validate(opA, opB, M, N, K, az ? zero : l, A, lda, B, ldb, bl, C, ldc, 4 * sizeof(T),
+                                4 * sizeof(T));
     if (s != QGEMM_OK) {
         static const int remap[14] = {0, 1, 2, 3, 4, 5, 6, 9, 10, 11, 12, 13, 15, 16};
         g_bad_arg = remap[g_bad_arg];
@@ -285,6 +331,9 @@ qgemm_status_t herk_impl(int uplo, int trans, int64_t N, int64_t K, double alpha
     if (!C) return fail(QGEMM_ERR_INVALID_ARG, 9);
     if (reads_a && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 6);
     if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 9);
+    if (reads_a && ranges_overlap(C, ldc, N, N, 4 * sizeof(T), A, lda, rows_a, trans == QGEMM_OP_N ? K : N,
+                                  4 * sizeof(T)))
+        return fail(QGEMM_ERR_INVALID_ARG, 9);
     const bool ta = trans == QGEMM_OP_C;
     const bool ld_ok = sizeof(T) == 4 ? qg::split_ld_supported(lda, lda, ta, !ta) : qg::f64_ld_supported(lda, lda, ta, !ta);
     if (!ld_ok) return fail(QGEMM_ERR_UNSUPPORTED, 7);
@@ -297,17 +346,6 @@ qgemm_status_t herk_impl(int uplo, int trans, int64_t N, int64_t K, double alpha
     if constexpr (sizeof(T) == 8) e = qg::launch_qgemm_f64(d, stream);
     else e = qg::launch_qgemm_bf16x3(d, nullptr, split_terms, qg::kSplitPanel, stream);
     return e == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
-}
-
-// Whether the bytes spanned by two column-major quaternion matrices (X: xrows x
-// xcols with leading dimension ldx, likewise Y) overlap.
-bool ranges_overlap(const void *X, int64_t ldx, int64_t xrows, int64_t xcols, const void *Y, int64_t ldy,
-                    int64_t yrows, int64_t ycols, int64_t qbytes)
-{
-    const uintptr_t x0 = reinterpret_cast<uintptr_t>(X), y0 = reinterpret_cast<uintptr_t>(Y);
-    const uintptr_t x1 = x0 + (uintptr_t)((ldx * (xcols - 1) + xrows) * qbytes);
-    const uintptr_t y1 = y0 + (uintptr_t)((ldy * (ycols - 1) + yrows) * qbytes);
-    return x0 < y1 && y0 < x1;
 }
 
 // Triangular multiply on the GEMM kernels: the triangular matrix is op(A)
@@ -346,8 +384,8 @@ qgemm_status_t trmm_impl(int side, int uplo, int trans, int diag, int64_t M, int
     if (reads_ab && (reinterpret_cast<uintptr_t>(B) % align)) return fail(QGEMM_ERR_MISALIGNED, 10);
     if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 12);
     // C is written while A and B are still read by other tiles: no overlap
-    if (reads_ab && (ranges_overlap(C, ldc, M, N, A, lda, n, n, 4 * sizeof(T)) ||
-                     ranges_overlap(C, ldc, M, N, B, ldb, M, N, 4 * sizeof(T))))
+    if (reads_ab && (ranges_overlap(C, ldc, M, N, 4 * sizeof(T), A, lda, n, n, 4 * sizeof(T)) ||
+                     ranges_overlap(C, ldc, M, N, 4 * sizeof(T), B, ldb, M, N, 4 * sizeof(T))))
         return fail(QGEMM_ERR_INVALID_ARG, 12);
     const bool left = side == QGEMM_SIDE_LEFT;
     const bool ta = left ? op_transposes(trans) : false, tb = left ? false : op_transposes(trans);
@@ -369,7 +407,7 @@ qgemm_status_t trmm_impl(int side, int uplo, int trans, int diag, int64_t M, int
 // Bytes spanned by n strided quaternions of `qbytes` bytes each.
 bool vec_overlap(const void *X, int64_t nx, int64_t incx, const void *Y, int64_t ny, int64_t incy, int64_t qbytes)
 {
-    return ranges_overlap(X, incx, 1, nx, Y, incy, 1, ny, qbytes);
+    return ranges_overlap(X, incx, 1, nx, qbytes, Y, incy, 1, ny, qbytes);
 }
 
 template <typename T>
@@ -444,7 +482,7 @@ qgemm_status_t gemv_impl(int trans, int64_t M, int64_t N, const double *alpha, c
     if (!alpha_zero && (reinterpret_cast<uintptr_t>(x) % align)) return fail(QGEMM_ERR_MISALIGNED, 7);
     if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 10);
     if (!alpha_zero && (vec_overlap(x, nx, incx, y, ny, incy, 4 * sizeof(T)) ||
-                        ranges_overlap(A, lda, M, N, y, incy, 1, ny, 4 * sizeof(T))))
+                        ranges_overlap(A, lda, M, N, 4 * sizeof(T), y, incy, 1, ny, 4 * sizeof(T))))
         return fail(QGEMM_ERR_INVALID_ARG, 10);
     return qg::launch_qgemv<T>(trans, (int)M, (int)N, alpha, A, lda, x, incx, beta, y, incy, stream) == hipSuccess
                ? QGEMM_OK
@@ -474,7 +512,7 @@ qgemm_status_t qgemm_d(int opA, int opB, int64_t M, int64_t N, int64_t K, const 
                        const double *A, int64_t lda, const double *B, int64_t ldb, const double *beta,
                        double *C, int64_t ldc, void *stream)
 {
-    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 32);
+    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 32, 32);
     if (s != QGEMM_OK || M == 0 || N == 0) return s;
     if (!qg::f64_ld_supported(lda, ldb, op_transposes(opA), op_transposes(opB)))
         return fail(QGEMM_ERR_UNSUPPORTED, op_transposes(opA) ? 8 : 10);
@@ -488,7 +526,7 @@ static qgemm_status_t split_common(int opA, int opB, int64_t M, int64_t N, int64
                                    float *C, double *C64, int64_t ldc, int split_terms, void *stream)
 {
     const void *Cv = C64 ? static_cast<const void *>(C64) : static_cast<const void *>(C);
-    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, Cv, ldc, C64 ? 32 : 16);
+    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, Cv, ldc, C64 ? 32 : 16, 16);
     if (s != QGEMM_OK) return s;
     if (split_terms == 0) split_terms = 6;
     if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 14);
@@ -571,13 +609,20 @@ qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, 
     if (!valid_type(typeA)) return fail(QGEMM_ERR_INVALID_ARG, 1);
     if (!valid_type(typeB)) return fail(QGEMM_ERR_INVALID_ARG, 2);
     if (typeA != QGEMM_QUATERNION && typeB != QGEMM_QUATERNION) return fail(QGEMM_ERR_INVALID_ARG, 2);
-    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 8);
+    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 8, 0);
     if (s != QGEMM_OK) return fail(s, g_bad_arg + 2);
     if (M == 0 || N == 0) return QGEMM_OK;
     const bool reads_ab = K > 0 && !is_zero4(alpha);
     if (reads_ab && (reinterpret_cast<uintptr_t>(A) % (8u * typeA))) return fail(QGEMM_ERR_MISALIGNED, 9);
     if (reads_ab && (reinterpret_cast<uintptr_t>(B) % (8u * typeB))) return fail(QGEMM_ERR_MISALIGNED, 11);
     if (reinterpret_cast<uintptr_t>(C) % 32u) return fail(QGEMM_ERR_MISALIGNED, 14);
+    if (reads_ab) {
+        const int64_t ra = op_transposes(opA) ? K : M, ca = op_transposes(opA) ? M : K;
+        const int64_t rb = op_transposes(opB) ? N : K, cb = op_transposes(opB) ? K : N;
+        if (ranges_overlap(C, ldc, M, N, 32, A, lda, ra, ca, 8 * typeA) ||
+            ranges_overlap(C, ldc, M, N, 32, B, ldb, rb, cb, 8 * typeB))
+            return fail(QGEMM_ERR_INVALID_ARG, 14);
+    }
     if (typeA == QGEMM_QUATERNION && typeB == QGEMM_QUATERNION) {
         s = qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
         return s == QGEMM_OK ? s : fail(s, g_bad_arg + 2);
@@ -685,7 +730,7 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
     if (tile_class >= qg::kGroupedClasses) return fail(QGEMM_ERR_INVALID_ARG, 9);
     for (int64_t i = 0; i < count; ++i) {
         const qgemm_problem_t &q = problems[i];
-        qgemm_status_t s = validate(opA, opB, q.M, q.N, q.K, alpha, q.A, q.lda, q.B, q.ldb, beta, q.C, q.ldc, 16);
+        qgemm_status_t s = validate(opA, opB, q.M, q.N, q.K, alpha, q.A, q.lda, q.B, q.ldb, beta, q.C, q.ldc, 16, 16);
         if (s != QGEMM_OK) {
             g_bad_problem = i;
             return s;

@@ -38,13 +38,9 @@ hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, hipStream_
 {
     auto kern = &qgemm_bf16x3_kernel<TA, TB, NTERMS, C64, STAGES, TRI>;
     constexpr size_t lds_bytes = STAGES == 1 ? TL::LDS_BYTES_1 : TL::LDS_BYTES;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> lds_set{0};
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(kern), (int)lds_bytes, lds_set);
+    if (e != hipSuccess) return e;
     const int tiles_m = (d.M + TL::BM - 1) / TL::BM;
     const int tiles_n = (d.N + TL::BN - 1) / TL::BN;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;

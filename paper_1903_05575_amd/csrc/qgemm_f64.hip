@@ -304,13 +304,10 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
 template <bool TA, bool TB, bool BS, int TRI>
 hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB, BS, TRI>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> lds_set{0};
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB, BS, TRI>),
+                                      (int)LDS_BYTES, lds_set);
+    if (e != hipSuccess) return e;
     const int tiles_m = (d.M + BM - 1) / BM;
     const int tiles_n = (d.N + BN - 1) / BN;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;

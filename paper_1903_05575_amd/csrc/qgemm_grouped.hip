@@ -113,12 +113,8 @@ int bucket_k(int64_t x) { return x <= 64 ? 0 : 1; }
 template <bool TA, bool TB, int NTERMS>
 hipError_t set_attr()
 {
-    static bool done = false;
-    if (done) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&grouped_kernel<TA, TB, NTERMS>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds);
-    if (e == hipSuccess) done = true;
-    return e;
+    static std::atomic<uint64_t> lds_set{0};
+    return ensure_dynamic_lds(reinterpret_cast<const void *>(&grouped_kernel<TA, TB, NTERMS>), (int)kLds, lds_set);
 }
 
 template <int NTERMS>

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/qgemm.h"
 #include "qgemm_device.hpp"
 
@@ -42,6 +44,22 @@ struct GemmDesc {
     double alpha_r[4];     // right scalars: C <- alpha acc alpha_r + beta C beta_r
     double beta_r[4];
 };
+
+// Raise the dynamic LDS limit of kernel `kern` to `bytes` on the current
+// device, once per device: the attribute is per device, so a process that
+// drives several GPUs sets it on each; `done` holds one bit per device
+// ordinal and makes later launches free.  Safe to call from several threads.
+inline hipError_t ensure_dynamic_lds(const void *kern, int bytes, std::atomic<uint64_t> &done)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const uint64_t bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0ull;
+    if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
 
 // Launch helpers (return a hipError_t from the launch).
 hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream);

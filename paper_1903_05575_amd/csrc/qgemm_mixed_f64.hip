@@ -244,13 +244,9 @@ hipError_t launch_t(const MixedDesc &d, hipStream_t stream)
 {
     using S = Shape<KC>;
     auto kern = &qgemm_mixed_f64_kernel<KC, RIGHT, XT, YT>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)S::LDS_BYTES);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<uint64_t> lds_set{0};
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(kern), (int)S::LDS_BYTES, lds_set);
+    if (e != hipSuccess) return e;
     const int tiles_p = (d.P + BP - 1) / BP;
     const int tiles_q = (d.Q + BQ - 1) / BQ;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;

@@ -37,9 +37,10 @@ def q4(*v):
 
 ONE = q4(1, 0, 0, 0)
 FAKE = 0x10000        # aligned, never dereferenced: validation fails first
+FAR_A, FAR_B, FAR_C = 1 << 40, 2 << 40, 3 << 40   # disjoint however large the leading dimensions
 
 
-def call_d(L, opA=0, opB=0, M=4, N=4, K=4, alpha=ONE, A=FAKE, lda=4, B=FAKE, ldb=4, beta=ONE, C=FAKE, ldc=4):
+def call_d(L, opA=0, opB=0, M=4, N=4, K=4, alpha=ONE, A=FAR_A, lda=4, B=FAR_B, ldb=4, beta=ONE, C=FAR_C, ldc=4):
     return L.qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, None)
 
 
@@ -47,7 +48,7 @@ def call_d(L, opA=0, opB=0, M=4, N=4, K=4, alpha=ONE, A=FAKE, lda=4, B=FAKE, ldb
     (dict(opA=7), 1, 1), (dict(opB=-1), 2, 1), (dict(M=-1), 3, 1), (dict(N=-2), 4, 1), (dict(K=-3), 5, 1),
     (dict(M=1 << 31), 3, 5), (dict(alpha=None), 6, 1), (dict(lda=3), 8, 1), (dict(ldb=3), 10, 1),
     (dict(beta=None), 11, 1), (dict(ldc=3), 13, 1), (dict(A=None), 7, 1), (dict(B=None), 9, 1),
-    (dict(C=None), 12, 1), (dict(A=FAKE + 8), 7, 2), (dict(B=FAKE + 16), 9, 2), (dict(C=FAKE + 24), 12, 2),
+    (dict(C=None), 12, 1), (dict(A=FAR_A + 8), 7, 2), (dict(B=FAR_B + 16), 9, 2), (dict(C=FAR_C + 24), 12, 2),
 ])
 def test_validation_d(L, kw, arg, status):
     rc = call_d(L, **kw)
@@ -68,9 +69,9 @@ def test_transposed_ld_rules(L):
 
 
 def test_validation_s_split_terms(L):
-    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, 4, ONE, FAKE, 4, 5, None)
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE_B, 4, ONE, FAKE_C, 4, 5, None)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 14
-    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE + 8, 4, FAKE, 4, ONE, FAKE, 4, 6, None)
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE + 8, 4, FAKE_B, 4, ONE, FAKE_C, 4, 6, None)
     assert rc == 2 and L.qgemm_last_invalid_arg() == 7
 
 
@@ -87,7 +88,7 @@ def test_batched_plan_validation(L):
     import paper_1903_05575_amd._lib as lb
     probs = (lb.Problem * 3)()
     for i in range(3):
-        probs[i] = lb.Problem(4, 4, 4, 4, 4, 4, FAKE, FAKE, FAKE)
+        probs[i] = lb.Problem(4, 4, 4, 4, 4, 4, FAKE, FAKE_B, FAKE_C + 4096 * i)
     probs[1].ldb = 2
     h = ctypes.c_void_p()
     rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
@@ -98,6 +99,9 @@ def test_batched_plan_validation(L):
     assert rc == 2 and L.qgemm_last_invalid_arg() == 12 and L.qgemm_last_invalid_problem() == 2
     rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, 5)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 9
+    probs[2].C = FAKE_B + 64                     # C of problem 2 inside its B
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 12 and L.qgemm_last_invalid_problem() == 2
     assert L.qgemm_batched_run(None, None) == 1
     assert L.qgemm_batched_plan_destroy(None) == 0
 
@@ -122,9 +126,9 @@ def test_split_unsupported_leading_dimension(L):
     """The split-BF16 tiles address a K-tile with 32-bit offsets: a transposed
     operand with lda >= 2^21 quaternions is refused as unsupported (host check)."""
     big = 1 << 21
-    rc = L.qgemm_s(1, 0, 4, 4, 4, ONE, FAKE, big, FAKE, 4, ONE, FAKE, 4, 6, None)
+    rc = L.qgemm_s(1, 0, 4, 4, 4, ONE, FAR_A, big, FAR_B, 4, ONE, FAR_C, 4, 6, None)
     assert rc == 5 and L.qgemm_last_invalid_arg() == 8
-    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, big * 4, ONE, FAKE, 4, 6, None)
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAR_A, 4, FAR_B, big * 4, ONE, FAR_C, 4, 6, None)
     assert rc == 5 and L.qgemm_last_invalid_arg() == 10
 
 
@@ -144,7 +148,7 @@ def test_validation_ex(L):
     assert rc == 2 and L.qgemm_last_invalid_arg() == 15
     rc = L.qgemm_ex_d(0, 0, 4, 4, 4, n, n, n, FAKE, 4, FAKE, 4, n, n, FAKE, 2, n)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 16
-    rc = L.qgemm_ex_s(0, 0, 4, 4, 4, n, n, n, FAKE, 4, FAKE, 4, n, n, FAKE, 4, 7, n)
+    rc = L.qgemm_ex_s(0, 0, 4, 4, 4, n, n, n, FAR_A, 4, FAR_B, 4, n, n, FAR_C, 4, 7, n)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 17
     # a zero middle scalar: A and B are not read, so NULL is accepted (N = 0: nothing launched)
     rc = L.qgemm_ex_d(0, 0, 4, 0, 4, n, q4(0, 0, 0, 0), n, None, 4, None, 4, n, n, FAKE, 4, n)
@@ -270,3 +274,29 @@ def test_validation_level12(L):
     assert gv(A=FAKE + 8) == (2, 5)
     assert gv(M=0, A=None, x=None, y=None) == (0, 0)
     assert gv(alpha=q4(0, 0, 0, 0), A=None, x=None, y=None) == (0, 0)   # alpha = 0, beta = 1
+
+
+def test_outputs_must_not_overlap_inputs(L):
+    """Every output is checked against the address ranges of what the call
+    reads (the kernels write some tiles while others still read)."""
+    # qgemm_d: C inside A (4 x 4 doubles quaternions span 512 bytes), C inside B, C == A
+    assert call_d(L, A=FAKE, C=FAKE + 256) == 1 and L.qgemm_last_invalid_arg() == 12
+    assert call_d(L, B=FAKE, C=FAKE + 256) == 1 and L.qgemm_last_invalid_arg() == 12
+    assert call_d(L, A=FAKE, B=FAKE, C=FAKE_C, M=0) == 0          # empty output: nothing to check
+    # qgemm_s / qgemm_ex_d / qgemm_mixed_d
+    assert L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE_B, 4, ONE, FAKE_B + 64, 4, 6, None) == 1
+    assert L.qgemm_last_invalid_arg() == 12
+    assert L.qgemm_ex_d(0, 0, 4, 4, 4, ONE, None, None, FAKE, 4, FAKE_B, 4, ONE, None, FAKE, 4, None) == 1
+    assert L.qgemm_last_invalid_arg() == 15
+    assert call_mixed(L, C=FAKE) == 1 and L.qgemm_last_invalid_arg() == 14
+    assert call_mixed(L, tA=1, tB=4, A=FAKE_C + 96, lda=4) == 1 and L.qgemm_last_invalid_arg() == 14
+    # qherk_d: C over A
+    d = ctypes.c_double
+    assert L.qherk_d(0, 0, 4, 4, d(1.0), FAKE, 4, d(0.0), FAKE + 32, 4, None) == 1
+    assert L.qgemm_last_invalid_arg() == 9
+    # backward: dA over G, dB over A, dC0 over dA
+    G = 0x50000
+    args = lambda dA, dB, dC0: (0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE_B, 4, G, 4, ONE, dA, 4, dB, 4, dC0, 4, None)
+    assert L.qgemm_backward_d(*args(G + 32, None, None)) == 1 and L.qgemm_last_invalid_arg() == 14
+    assert L.qgemm_backward_d(*args(None, FAKE, None)) == 1 and L.qgemm_last_invalid_arg() == 16
+    assert L.qgemm_backward_d(*args(0x60000, None, 0x60000 + 128)) == 1 and L.qgemm_last_invalid_arg() == 18
