@@ -737,13 +737,20 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
         }
     }
     qg::GroupedPlan *impl = nullptr;
-    int rc = qg::grouped_plan_create(&impl, op_transposes(opA), op_transposes(opB), op_conjugates(opA),
+    int rc;
+    try {   // host containers may throw; nothing crosses the C ABI
+        rc = qg::grouped_plan_create(&impl, op_transposes(opA), op_transposes(opB), op_conjugates(opA),
                                      op_conjugates(opB), split_terms, alpha, beta, count, problems, tile_class);
+    } catch (const std::bad_alloc &) {
+        return QGEMM_ERR_ALLOC;
+    } catch (...) {
+        return QGEMM_ERR_HIP;
+    }
     if (rc < 0) {
         g_bad_problem = -(int64_t)rc - 1;
         return fail(QGEMM_ERR_UNSUPPORTED, 5);
     }
-    if (rc != QGEMM_OK) return (qgemm_status_t)rc;
+    if (rc != QGEMM_OK) return fail((qgemm_status_t)rc, rc == QGEMM_ERR_UNSUPPORTED ? 5 : 0);
     qgemm_plan_s *h = new (std::nothrow) qgemm_plan_s{impl};
     if (!h) {
         qg::grouped_plan_destroy(impl);

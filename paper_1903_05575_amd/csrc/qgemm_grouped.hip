@@ -19,6 +19,7 @@
 #include <new>
 #include <numeric>
 #include <queue>
+#include <memory>
 #include <vector>
 
 namespace qg {
@@ -156,12 +157,17 @@ int grouped_tile_class(int64_t M, int64_t N, int64_t K) { return kTileTable[buck
 
 // Build a plan.  `probs` have been validated by the caller.  force_class < 0
 // selects the tile class from the table, otherwise it is used for every
-// problem.  Returns QGEMM_OK, QGEMM_ERR_ALLOC or QGEMM_ERR_HIP.
+// problem.  Returns QGEMM_OK, QGEMM_ERR_ALLOC, QGEMM_ERR_HIP,
+// QGEMM_ERR_UNSUPPORTED (more than 2^31 - 1 tiles), or -(i + 1) when the
+// leading dimensions of problem i are beyond the tile addressing.  Host
+// containers may throw std::bad_alloc; the C-ABI caller turns that into
+// QGEMM_ERR_ALLOC.
 int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, int nterms, const double alpha[4],
                         const double beta[4], int64_t count, const ::qgemm_problem_t *probs, int force_class)
 {
-    GroupedPlan *pl = new (std::nothrow) GroupedPlan();
-    if (!pl) return QGEMM_ERR_ALLOC;
+    std::unique_ptr<GroupedPlan> owner(new (std::nothrow) GroupedPlan());
+    if (!owner) return QGEMM_ERR_ALLOC;
+    GroupedPlan *pl = owner.get();
     pl->ta = ta;
     pl->tb = tb;
     pl->s.conjA = ca ? 1 : 0;
@@ -189,10 +195,8 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         d.pad = 0;
         if (q.M == 0 || q.N == 0) continue;
         const int cls = force_class >= 0 ? force_class : grouped_tile_class(q.M, q.N, q.K);
-        if (!split::split_offsets_fit(q.lda, q.ldb, ta, tb, kBM[cls], kBN[cls], kBK)) {
-            delete pl;
+        if (!split::split_offsets_fit(q.lda, q.ldb, ta, tb, kBM[cls], kBN[cls], kBK))
             return -(int)(i + 1);                  // caller reports QGEMM_ERR_UNSUPPORTED for problem i
-        }
         const int tm = (int)((q.M + kBM[cls] - 1) / kBM[cls]);
         const int tn = (int)((q.N + kBN[cls] - 1) / kBN[cls]);
         const int64_t kp = ((q.K + kBK - 1) / kBK) * kBK;
@@ -205,12 +209,11 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         pl->class_count[cls] += (int64_t)tm * tn;
     }
     pl->nitems = (int64_t)items.size();
-    if (hipGetDevice(&pl->device) != hipSuccess) { delete pl; return QGEMM_ERR_HIP; }
+    if (pl->nitems > 0x7fffffff) return QGEMM_ERR_UNSUPPORTED;   // item indices and block starts are 32-bit
+    if (hipGetDevice(&pl->device) != hipSuccess) return QGEMM_ERR_HIP;
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
-        delete pl;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess)
         return QGEMM_ERR_HIP;
-    }
     const int64_t G = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * kBlocksPerCU, pl->nitems));
     pl->grid = (int)G;
     // longest processing time first: each item to the least loaded block
@@ -240,8 +243,7 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         (void)hipFree(pl->d_probs);
         (void)hipFree(pl->d_items);
         (void)hipFree(pl->d_starts);
-        delete pl;
-        return code;
+        return code;                               // `owner` deletes the plan
     };
     if (hipMalloc(&pl->d_probs, sizeof(DevProblem) * std::max<size_t>(1, hp.size())) != hipSuccess)
         return fail(QGEMM_ERR_ALLOC);
@@ -256,7 +258,7 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         return fail(QGEMM_ERR_HIP);
     if (hipMemcpy(pl->d_starts, starts.data(), sizeof(int) * starts.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(QGEMM_ERR_HIP);
-    *out = pl;
+    *out = owner.release();
     return QGEMM_OK;
 }
 
