@@ -51,6 +51,10 @@
  *   - Threads and devices: calls from several host threads are safe; each
  *     call runs on the calling thread's current device (set up once per
  *     device on first use) and on the given stream, in stream order.
+ *   - Graph capture: every entry point except qgemm_batched_plan_create and
+ *     qgemm_batched_plan_destroy only launches kernels (no allocation, host
+ *     copy, memset or synchronisation), so its work may be captured into a
+ *     hipGraph and replayed; scalars are frozen into the captured launch.
  */
 #ifndef QGEMM_H
 #define QGEMM_H
