@@ -126,3 +126,32 @@ def test_sweep_8192_sampled(gpu, opA, opB):
     bound = (4 * n + 8) * 2.0 ** -53 * (np.abs(p["alpha"]).sum() * S + np.abs(p["beta"]).sum() * c1)
     err = np.abs(gs - want).transpose(1, 0, 2)
     assert (err <= bound[..., None]).all()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("opA,opB", [("T", "N"), ("N", "N"), ("C", "T")])
+def test_largest_supported_leading_dimension(gpu, opA, opB):
+    """The largest leading dimension the 32-bit in-tile offsets allow
+    (2^20 - 1 quaternions: a 64-wide tile of a transposed A, or of B with op N,
+    spans just under 2^31 bytes): exact parity, no offset wrap."""
+    ld = (1 << 20) - 1
+    M, N, K = 70, 66, 12
+    g = W.rng(1500 + "NTC".index(opA) * 3 + "NTC".index(opB))
+    ra, ca = (M, K) if opA == "N" else (K, M)
+    rb, cb = (K, N) if opB == "N" else (N, K)
+    A = np.full((ca, ld, 4), np.nan)
+    A[:, :ra] = g.uniform(-1, 1, (ca, ra, 4))
+    B = np.full((cb, ld, 4), np.nan)
+    B[:, :rb] = g.uniform(-1, 1, (cb, rb, 4))
+    C = W.qmatrix(g, M, N, ld=M + 1)
+    al, be = W.quaternion(g), W.quaternion(g)
+    # the oracle gets the same logical operands, compactly stored
+    want = oracle.qgemm(opA, opB, M, N, K, al, A[:, :ra].copy(), ra, B[:, :rb].copy(), rb, be, C, M + 1)
+    Cd, Ad, Bd = dev(C), dev(A), dev(B)
+    q.qgemm_d(opA, opB, M, N, K, al, Ad, ld, Bd, ld, be, Cd, M + 1)
+    assert relfro(logical(host(Cd), M, N), logical(want, M, N)) <= 1e-13
+    # one more on the operand whose tile spans the full leading dimension is refused, not wrapped
+    lda, ldb = (ld + 1, ld) if opA in "TC" else (ld, ld + 1)
+    with pytest.raises(q.QGemmError) as e:
+        q.qgemm_d(opA, opB, M, N, K, al, Ad, lda, Bd, ldb, be, Cd, M + 1)
+    assert e.value.status == 5

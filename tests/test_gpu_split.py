@@ -110,3 +110,29 @@ def test_precision_4096_sampled(gpu, scaled):
     err = relfro(got[cols][:, rows], want)
     print(f"precision 4096 scaled={scaled}: sampled rel err {err:.3e}")
     assert err <= BOUND[6]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("opA,opB", [("T", "N"), ("N", "N")])
+def test_split_largest_supported_leading_dimension(gpu, opA, opB):
+    """The split tiles' 32-bit in-tile offsets allow leading dimensions up to
+    2^21 - 1 quaternions for a transposed A or B with op N: exact parity at the
+    limit, refusal one past it."""
+    ld = (1 << 21) - 1
+    M, N, K = 70, 66, 20
+    g = W.rng(1520 + (opA == "T"))
+    ra, ca = (M, K) if opA == "N" else (K, M)
+    A = np.full((ca, ld, 4), np.nan, dtype=np.float32)
+    A[:, :ra] = g.standard_normal((ca, ra, 4))
+    B = np.full((N, ld, 4), np.nan, dtype=np.float32)
+    B[:, :K] = g.standard_normal((N, K, 4))
+    C = W.qmatrix(g, M, N, ld=M, dtype=np.float32)
+    al, be = W.quaternion(g), W.quaternion(g)
+    want = oracle.qgemm(opA, opB, M, N, K, al, A[:, :ra].copy(), ra, B[:, :K].copy(), K, be, C, M)
+    Cd, Ad, Bd = dev(C), dev(A), dev(B)
+    q.qgemm_s(opA, opB, M, N, K, al, Ad, ld, Bd, ld, be, Cd, M)
+    assert relfro(logical(host(Cd), M, N), logical(want, M, N)) <= 1e-6
+    lda, ldb = (ld + 1, ld) if opA == "T" else (ld, ld + 1)
+    with pytest.raises(q.QGemmError) as e:
+        q.qgemm_s(opA, opB, M, N, K, al, Ad, lda, Bd, ldb, be, Cd, M)
+    assert e.value.status == 5
