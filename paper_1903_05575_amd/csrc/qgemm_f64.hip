@@ -140,11 +140,17 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     // check (in-tile byte offsets are below 2^31, see f64_ld_supported)
     auto load_tile = [&](int kt) {
         const int k0 = kt * BK;
-        const int krem = p.K - k0;
+        // the prefetch past this tile's K-range reads nothing (for a triangular
+        // operand that tile lies in the triangle that must not be read)
+        const int krem = (kt < kt1 ? p.K : 0) - k0;
         const double *Ab = p.A + 4 * (TA ? ((int64_t)m0 * p.lda + k0) : ((int64_t)k0 * p.lda + m0));
         const double *Bb = p.B + 4 * (TB ? ((int64_t)k0 * p.ldb + n0) : ((int64_t)n0 * p.ldb + k0));
         const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, 0x7fffffff, 0x00020000);
         const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, 0x7fffffff, 0x00020000);
+        // only K-tiles that cross the diagonal of a triangular operand need its mask (uniform per block)
+        const bool diagA = TRI == 1 && k0 < m0 + BM && k0 + BK > m0;
+        const bool diagB = TRI == 2 && k0 < n0 + BN && k0 + BK > n0;
+        if constexpr (TRI != 0) unit_bits = 0;
 #pragma unroll
         for (int i = 0; i < A_CHUNKS; ++i) {
             int mu, ka, half;
@@ -152,14 +158,13 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
             const unsigned e = TA ? (unsigned)mu * (unsigned)p.lda + ka : (unsigned)ka * (unsigned)p.lda + mu;
             bool ok = m0 + mu < p.M && ka < krem;
             if constexpr (TRI == 1) {
-                const int gm = m0 + mu, gk = k0 + ka;
-                ok = ok && (p.tri_lower ? gk <= gm : gk >= gm) && !(p.tri_unit && gk == gm);
+                if (diagA) {
+                    const int gm = m0 + mu, gk = k0 + ka;
+                    ok = ok && (p.tri_lower ? gk <= gm : gk >= gm) && !(p.tri_unit && gk == gm);
+                    if (p.tri_unit && gk == gm && gm < p.M) unit_bits |= 1u << i;
+                }
             }
             ra[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rA, ok ? 32u * e + 16u * half : kOob, 0, 0));
-            if constexpr (TRI == 1) {
-                if (i == 0) unit_bits = 0;
-                if (p.tri_unit && m0 + mu == k0 + ka && m0 + mu < p.M) unit_bits |= 1u << i;
-            }
         }
 #pragma unroll
         for (int i = 0; i < B_QUATS; ++i) {
@@ -168,15 +173,14 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
             const unsigned e = TB ? (unsigned)ka * (unsigned)p.ldb + nu : (unsigned)nu * (unsigned)p.ldb + ka;
             bool ok = n0 + nu < p.N && ka < krem;
             if constexpr (TRI == 2) {
-                const int gn = n0 + nu, gk = k0 + ka;
-                ok = ok && (p.tri_lower ? gk >= gn : gk <= gn) && !(p.tri_unit && gk == gn);
+                if (diagB) {
+                    const int gn = n0 + nu, gk = k0 + ka;
+                    ok = ok && (p.tri_lower ? gk >= gn : gk <= gn) && !(p.tri_unit && gk == gn);
+                    if (p.tri_unit && gk == gn && gn < p.N) unit_bits |= 1u << i;
+                }
             }
             rb[i][0] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? 32u * e : kOob, 0, 0));
             rb[i][1] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? 32u * e + 16u : kOob, 0, 0));
-            if constexpr (TRI == 2) {
-                if (i == 0) unit_bits = 0;
-                if (p.tri_unit && n0 + nu == k0 + ka && n0 + nu < p.N) unit_bits |= 1u << i;
-            }
         }
     };
 

@@ -88,6 +88,9 @@ __global__ __launch_bounds__(split::NT, kBlocksPerCU) void grouped_kernel(const 
         d.has_right = false;
         d.uplo = 0;
         d.herm_diag = false;
+        d.tri = 0;
+        d.tri_lower = false;
+        d.tri_unit = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             d.alpha[i] = s.alpha[i];
