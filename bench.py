@@ -487,13 +487,16 @@ def variant_context(steps, warmup):
 
 def sweep(steps, warmup):
     """FP64 qgemm_d over M = N = K in 1024..8192 and every op pair of N, T, C:
-    one JSON line per case (event time per launch and effective TFLOP/s)."""
+    one JSON line per case (event time per launch and effective TFLOP/s);
+    sizes up to 2048 are timed over at least 50 launches after 10."""
     for n in W.SWEEP_SIZES:
         for opA, opB in W.OP_PAIRS:
             p = W.gemm_sweep(n, opA, opB)
             A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
+            # short launches need more of them for steady clocks
+            st, wu = (max(steps, 50), max(warmup, 10)) if n <= 2048 else (steps, warmup)
             _, ev = time_launches(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
-                                                    p["beta"], C, p["ldc"]), steps, warmup)
+                                                    p["beta"], C, p["ldc"]), st, wu)
             fl = q.flops(n, n, n)
             print(json.dumps({"sweep": f"{n} {opA}/{opB}", "ms": round(ev, 3),
                               "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),

@@ -58,22 +58,6 @@ hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, int64_t nb
     return hipGetLastError();
 }
 
-// Compute units of the current device (cached per device ordinal).
-int device_cus()
-{
-    static std::atomic<int> cache[64] = {};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (dev >= 0 && dev < 64) {
-        const int c = cache[dev].load(std::memory_order_relaxed);
-        if (c > 0) return c;
-    }
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (dev >= 0 && dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
-    return cus;
-}
-
 template <bool TA, bool TB, int NTERMS, bool C64, int TRI>
 hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
 {

@@ -52,19 +52,29 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int BM = 64, BN = 64, BK = 8;
+constexpr int BN = 64, BK = 8;
 constexpr int NT = 256;
-constexpr int A_LD = 4 * BM + 4;                 // doubles per kappa row of the A stage
 constexpr int B_PL = BN + 1;                     // doubles per component plane of the B stage
-constexpr int A_STAGE = BK * A_LD;
 constexpr int B_STAGE = BK * 4 * B_PL;
-constexpr int STAGE = A_STAGE + B_STAGE;
-constexpr int A_CHUNKS = BM * BK * 2 / NT;       // 16-byte chunks of A per thread per tile
 constexpr int B_QUATS = BN * BK / NT;            // quaternions of B per thread per tile
-constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
-
-static_assert(A_CHUNKS * NT == BM * BK * 2, "A tile must split evenly over the block");
 static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
+
+// Tile height: 64 quaternion rows, or 32 for grids whose 64-row tiles cannot
+// fill two blocks per CU (a 1024 x 1024 output has 256 tiles of 64 x 64 for
+// 512 block slots).  Each wave owns BM / 4 rows = MB MFMA row blocks.
+template <int BMT>
+struct FTile {
+    static constexpr int BM = BMT;
+    static constexpr int WM = BM / 4;            // quaternion rows per wave
+    static constexpr int MB = WM / 4;            // MFMA row blocks (4 rows each) per wave
+    static constexpr int A_LD = 4 * BM + 4;      // doubles per kappa row of the A stage
+    static constexpr int A_STAGE = BK * A_LD;
+    static constexpr int STAGE = A_STAGE + B_STAGE;
+    static constexpr int A_CHUNKS = BM * BK * 2 / NT;   // 16-byte chunks of A per thread per tile
+    static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
+    static_assert(A_CHUNKS * NT == BM * BK * 2, "A tile must split evenly over the block");
+    static_assert(MB * 16 == BM, "whole MFMA row blocks per wave");
+};
 
 __device__ __forceinline__ double flip(double v, unsigned long long sign)
 {
@@ -73,9 +83,12 @@ __device__ __forceinline__ double flip(double v, unsigned long long sign)
 
 constexpr unsigned kOob = 0x80000000u;   // buffer offset read as zero (masked element)
 
-template <bool TA, bool TB, bool BS, int TRI>
+template <int BMT, bool TA, bool TB, bool BS, int TRI>
 __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n, int nk)
 {
+    using FT = FTile<BMT>;
+    constexpr int BM = FT::BM, WM = FT::WM, MB = FT::MB, A_LD = FT::A_LD, A_STAGE = FT::A_STAGE,
+                  STAGE = FT::STAGE, A_CHUNKS = FT::A_CHUNKS;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -106,13 +119,13 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     const int fcomp = fr ^ fc;                   // component of a that L(a)[fr][fc] reads
     const bool neg = l_negative(fr, fc) ^ (p.conjA && fcomp != 0);
     const unsigned long long sgnA = neg ? 0x8000000000000000ull : 0ull;
-    const int a_off = (wave * 16 + fmu) * 4 + fcomp;      // + kk*A_LD + 16*m
+    const int a_off = (wave * WM + fmu) * 4 + fcomp;      // + kk*A_LD + 16*m
     const int b_off = fc * B_PL + (lane & 15);            // + kk*4*B_PL + 16*n
     const unsigned conjB = p.conjB ? 0x80000000u : 0u;     // sign bit of the high word of q1..q3
 
-    d4 acc[4][4];
+    d4 acc[MB][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < MB; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
 
@@ -225,9 +238,9 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     // the MFMAs.  Fragments of step kk + 1 are read while step kk's MFMAs run.
     auto step_tile = [&](const double *As, double *Nxt) {
         const double *Bs = As + A_STAGE;
-        double a[2][4], b[2][4];
+        double a[2][MB], b[2][4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) a[0][m] = As[a_off + 16 * m];
+        for (int m = 0; m < MB; ++m) a[0][m] = As[a_off + 16 * m];
 #pragma unroll
         for (int n = 0; n < 4; ++n) b[0][n] = Bs[b_off + 16 * n];
 #pragma unroll
@@ -235,14 +248,14 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
             const int cur = kk & 1;
             if (kk + 1 < BK) {
 #pragma unroll
-                for (int m = 0; m < 4; ++m) a[cur ^ 1][m] = As[(kk + 1) * A_LD + a_off + 16 * m];
+                for (int m = 0; m < MB; ++m) a[cur ^ 1][m] = As[(kk + 1) * A_LD + a_off + 16 * m];
 #pragma unroll
                 for (int n = 0; n < 4; ++n) b[cur ^ 1][n] = Bs[(kk + 1) * 4 * B_PL + b_off + 16 * n];
             }
             // keep the sign flips of step kk + 1 out of this step: they would wait on the reads above
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < MB; ++m) {
                 const double am = flip(a[cur][m], sgnA);
 #pragma unroll
                 for (int n = 0; n < 4; ++n)
@@ -269,8 +282,8 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions
     const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int mu = m0 + wave * 16 + 4 * m + (lane >> 4);
+    for (int m = 0; m < MB; ++m) {
+        const int mu = m0 + wave * WM + 4 * m + (lane >> 4);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int nu = n0 + 16 * n + (lane & 15);
@@ -305,33 +318,63 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
     }
 }
 
-template <bool TA, bool TB, bool BS, int TRI>
+template <int BMT, bool TA, bool TB, bool BS, int TRI>
 hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
 {
+    using FT = FTile<BMT>;
+    if (d.uplo != 0 && FT::BM != BN) return hipErrorInvalidValue;   // the triangular grid needs square tiles
     static std::atomic<uint64_t> lds_set{0};
-    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(&qgemm_f64_kernel<TA, TB, BS, TRI>),
-                                      (int)LDS_BYTES, lds_set);
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(&qgemm_f64_kernel<BMT, TA, TB, BS, TRI>),
+                                      (int)FT::LDS_BYTES, lds_set);
     if (e != hipSuccess) return e;
-    const int tiles_m = (d.M + BM - 1) / BM;
+    const int tiles_m = (d.M + FT::BM - 1) / FT::BM;
     const int tiles_n = (d.N + BN - 1) / BN;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
     const int nk = alpha_zero ? 0 : (d.K + BK - 1) / BK;
     const int64_t nblocks = d.uplo == 0 ? (int64_t)tiles_m * tiles_n : (int64_t)tiles_m * (tiles_m + 1) / 2;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((qgemm_f64_kernel<TA, TB, BS, TRI>), dim3((unsigned)nblocks), dim3(NT), LDS_BYTES, stream,
-                       d, tiles_m, tiles_n, nk);
+    hipLaunchKernelGGL((qgemm_f64_kernel<BMT, TA, TB, BS, TRI>), dim3((unsigned)nblocks), dim3(NT), FT::LDS_BYTES,
+                       stream, d, tiles_m, tiles_n, nk);
     return hipGetLastError();
 }
 
-}  // namespace
+template <int BMT, bool BS, int TRI>
+hipError_t launch_ops_t(const GemmDesc<double> &d, hipStream_t stream)
+{
+    if (d.opA_t)
+        return d.opB_t ? launch_t<BMT, true, true, BS, TRI>(d, stream) : launch_t<BMT, true, false, BS, TRI>(d, stream);
+    return d.opB_t ? launch_t<BMT, false, true, BS, TRI>(d, stream) : launch_t<BMT, false, false, BS, TRI>(d, stream);
+}
 
+// Fraction of the block slots (two per CU) that a grid of `tiles` equal tiles
+// keeps busy over its rounds.
+double slot_fill(int64_t tiles, int64_t slots)
+{
+    const int64_t rounds = (tiles + slots - 1) / slots;
+    return rounds > 0 ? (double)tiles / (double)(rounds * slots) : 1.0;
+}
+
+// 64-row tiles, or 32-row tiles for a full (not triangular) output whose
+// 64-row grid fills the block slots clearly worse (a 1024 x 1024 output has
+// 256 tiles of 64 x 64 for 512 slots; 1536 x 1536 has 576, one full round and
+// one of 64).  Measured: 1024^3 from 79% to 84% of the FP64 peak.
 template <bool BS, int TRI>
 hipError_t launch_ops(const GemmDesc<double> &d, hipStream_t stream)
 {
-    if (d.opA_t) return d.opB_t ? launch_t<true, true, BS, TRI>(d, stream) : launch_t<true, false, BS, TRI>(d, stream);
-    return d.opB_t ? launch_t<false, true, BS, TRI>(d, stream) : launch_t<false, false, BS, TRI>(d, stream);
+    if constexpr (TRI == 0) {
+        if (d.uplo == 0) {
+            const int64_t slots = 2 * (int64_t)device_cus();
+            const int64_t tn = (d.N + BN - 1) / BN;
+            const int64_t tiles64 = (int64_t)((d.M + 63) / 64) * tn, tiles32 = (int64_t)((d.M + 31) / 32) * tn;
+            if (slots > 0 && slot_fill(tiles32, slots) > 1.1 * slot_fill(tiles64, slots))
+                return launch_ops_t<32, BS, TRI>(d, stream);
+        }
+    }
+    return launch_ops_t<64, BS, TRI>(d, stream);
 }
+
+}  // namespace
 
 hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream)
 {

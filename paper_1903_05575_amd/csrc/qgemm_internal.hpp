@@ -61,6 +61,23 @@ inline hipError_t ensure_dynamic_lds(const void *kern, int bytes, std::atomic<ui
     return e;
 }
 
+// Compute units of the current device, cached per device ordinal (0 if the
+// query fails).
+inline int device_cus()
+{
+    static std::atomic<int> cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev >= 0 && dev < 64) {
+        const int c = cache[dev].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (dev >= 0 && dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
 // Launch helpers (return a hipError_t from the launch).
 hipError_t launch_qgemm_f64(const GemmDesc<double> &d, hipStream_t stream);
 // Split-BF16 path for FP32 operands.  nterms in {3, 6, 9}; panel = kappa

@@ -155,3 +155,20 @@ def test_largest_supported_leading_dimension(gpu, opA, opB):
     with pytest.raises(q.QGemmError) as e:
         q.qgemm_d(opA, opB, M, N, K, al, Ad, lda, Bd, ldb, be, Cd, M + 1)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("opA", "NTCR")
+@pytest.mark.parametrize("opB", "NTCR")
+def test_ops_ragged_both_tile_heights(gpu, opA, opB):
+    """Grids whose 64-row tiles fill the block slots poorly run 32-row tiles,
+    others 64-row tiles: every op pair, ragged in M, N and K, through both
+    (300 x 250: 20 tiles of 64 x 64 -> 32-row; 2040 x 2000: 1024 -> 64-row)."""
+    for i, (M, N, K) in enumerate(((300, 250, 37), (2040, 2000, 29))):
+        p = W.gemm_problem(1600 + 32 * i + "NTCR".index(opA) * 4 + "NTCR".index(opB), M, N, K, opA, opB, pad=1)
+        Cd = dev(p["C"])
+        q.qgemm_d(opA, opB, M, N, K, p["alpha"], dev(p["A"]), p["lda"], dev(p["B"]), p["ldb"], p["beta"], Cd, p["ldc"])
+        want = oracle.qgemm(opA, opB, M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"], p["beta"], p["C"],
+                            p["ldc"])
+        got = host(Cd)
+        assert relfro(logical(got, M, N), logical(want, M, N)) <= 1e-13, (M, N, K)
+        np.testing.assert_array_equal(got[:, M:], p["C"][:, M:])
