@@ -6,10 +6,13 @@
 //        barrier per K-tile) -- used when the grid fills two blocks per CU,
 //        where the other block covers each block's staging; measured 2-4%
 //        faster than TL1 there, and its op N/N instantiation does not spill;
+//   TL3: 32 x 64 tiles on the TL2 pipeline -- for full outputs whose 64-row
+//        grid fills the block slots clearly worse (e.g. 1024 x 1024 outputs:
+//        256 tiles of 64 x 64 for 512 slots);
 //   TL1: K-tiles of 16 quaternions through one LDS stage (two barriers per
-//        K-tile, half as many K-tiles) -- used for grids of fewer tiles
-//        (e.g. 1024 x 1024 outputs with a long K), where each CU holds one
-//        block and the per-K-tile overhead is exposed.
+//        K-tile, half as many K-tiles) -- for the remaining grids of fewer
+//        tiles than slots, where each CU holds one block and the per-K-tile
+//        overhead is exposed.
 #include "qgemm_bf16x3_tile.hpp"
 
 namespace qg {
@@ -17,6 +20,7 @@ namespace {
 
 using TL1 = split::Tile<64, 64, 4, 1, 16>;
 using TL2 = split::Tile<64, 64, 4, 1, 8>;
+using TL3 = split::Tile<32, 64, 4, 1, 8>;   // 32-row tiles for grids that 64-row tiles fill poorly
 
 template <class TL, bool TA, bool TB, int NTERMS, bool C64, int STAGES, int TRI>
 __global__ __launch_bounds__(split::NT, 2) void qgemm_bf16x3_kernel(GemmDesc<float> p, double *c64, int tiles_m,
@@ -58,10 +62,18 @@ hipError_t launch_s(const GemmDesc<float> &d, double *c64, int panel, int64_t nb
     return hipGetLastError();
 }
 
+// Fraction of the block slots (two per CU) that a grid of `tiles` equal tiles
+// keeps busy over its rounds.
+double slot_fill(int64_t tiles, int64_t slots)
+{
+    const int64_t rounds = (tiles + slots - 1) / slots;
+    return rounds > 0 ? (double)tiles / (double)(rounds * slots) : 1.0;
+}
+
 template <bool TA, bool TB, int NTERMS, bool C64, int TRI>
 hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_t stream)
 {
-    static_assert(TL1::BM == TL2::BM && TL1::BN == TL2::BN, "both pipelines use the same output tiles");
+    static_assert(TL1::BM == TL2::BM && TL1::BN == TL2::BN && TL3::BN == TL2::BN, "same tile widths");
     static_assert(TL1::BM == TL1::BN, "triangular launches need square tiles");
     const int tiles_m = (d.M + TL1::BM - 1) / TL1::BM;
     const int tiles_n = (d.N + TL1::BN - 1) / TL1::BN;
@@ -69,8 +81,13 @@ hipError_t launch_t(const GemmDesc<float> &d, double *c64, int panel, hipStream_
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
     if constexpr (TRI == 0) {
-        if (nblocks < 2 * (int64_t)device_cus())
-            return launch_s<TL1, TA, TB, NTERMS, C64, 1, TRI>(d, c64, panel, nblocks, stream);
+        const int64_t slots = 2 * (int64_t)device_cus();
+        if (d.uplo == 0 && slots > 0) {
+            const int64_t tiles32 = (int64_t)((d.M + TL3::BM - 1) / TL3::BM) * tiles_n;
+            if (slot_fill(tiles32, slots) > 1.1 * slot_fill(nblocks, slots))
+                return launch_s<TL3, TA, TB, NTERMS, C64, 2, TRI>(d, c64, panel, tiles32, stream);
+        }
+        if (nblocks < slots) return launch_s<TL1, TA, TB, NTERMS, C64, 1, TRI>(d, c64, panel, nblocks, stream);
     }
     return launch_s<TL2, TA, TB, NTERMS, C64, 2, TRI>(d, c64, panel, nblocks, stream);
 }
@@ -98,9 +115,10 @@ hipError_t dispatch_tri(const GemmDesc<float> &d, int nterms, int panel, hipStre
 
 hipError_t launch_qgemm_bf16x3(const GemmDesc<float> &d, double *c64, int nterms, int panel, hipStream_t stream)
 {
-    // both pipelines must address their K-tiles with 32-bit offsets
+    // every pipeline must address its K-tiles with 32-bit offsets
     if (!split::split_offsets_fit(d.lda, d.ldb, d.opA_t, d.opB_t, TL1::BM, TL1::BN, TL1::BK) ||
-        !split::split_offsets_fit(d.lda, d.ldb, d.opA_t, d.opB_t, TL2::BM, TL2::BN, TL2::BK))
+        !split::split_offsets_fit(d.lda, d.ldb, d.opA_t, d.opB_t, TL2::BM, TL2::BN, TL2::BK) ||
+        !split::split_offsets_fit(d.lda, d.ldb, d.opA_t, d.opB_t, TL3::BM, TL3::BN, TL3::BK))
         return hipErrorInvalidValue;
     if (d.tri != 0) {
         // a triangular operand is square and comes without a scale, a triangular output or an FP64 result
