@@ -320,9 +320,9 @@ qgemm_status_t qgemv_s(int trans, int64_t M, int64_t N, const double *alpha, con
  *   7 A, 8 lda, 9 B, 10 ldb, 12 C, 13 ldc -- and qgemm_last_invalid_problem()
  *   its index), builds the work table on the host and copies it to the
  *   current device (hipMalloc + synchronous copy: do NOT call it inside a
- *   stream capture).  tile_class < 0 uses the tuned table; 0..4 forces one
- *   class (0 = 64x64, 1 = 32x64, 2 = 64x32, 3 = 32x32, 4 = 16x64
- *   quaternions) for every problem.  The plan keeps the problem pointers and
+ *   stream capture).  tile_class < 0 uses the tuned table; 0..3 forces one
+ *   class (0 = 32x64, 1 = 64x32, 2 = 32x32, 3 = 16x64 quaternions) for
+ *   every problem.  The plan keeps the problem pointers and
  *   sizes: the buffers must stay valid while the plan is run.
  *   Arguments: 1 plan, 2 opA, 3 opB, 4 count, 5 problems, 6 alpha, 7 beta,
  *   8 split_terms, 9 tile_class.
@@ -349,7 +349,7 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
                                          const double *beta, int split_terms, int tile_class);
 qgemm_status_t qgemm_batched_run(qgemm_plan_t plan, void *stream);
 qgemm_status_t qgemm_batched_plan_destroy(qgemm_plan_t plan);
-/* Work items, grid size and tiles per class (array of 5) of a plan. */
+/* Work items, grid size and tiles per class (array of 4) of a plan. */
 qgemm_status_t qgemm_batched_plan_info(qgemm_plan_t plan, int64_t *work_items, int *grid,
                                        int64_t *class_counts);
 /* Index of the problem that made the last plan creation on this thread fail, or -1. */

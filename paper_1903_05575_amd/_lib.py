@@ -205,7 +205,7 @@ def qgemm_backward(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta,
         raise ValueError(f"unsupported dtype {dtype}")
 
 
-TILE_CLASSES = ((64, 64), (32, 64), (64, 32), (32, 32), (16, 64))
+TILE_CLASSES = ((32, 64), (64, 32), (32, 32), (16, 64))
 
 
 class GroupedPlan:

@@ -140,7 +140,7 @@ hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A
 
 // Grouped (batched) split-BF16 plans; see qgemm_grouped.hip.
 struct GroupedPlan;
-constexpr int kGroupedClasses = 5;
+constexpr int kGroupedClasses = 4;
 int grouped_tile_class(int64_t M, int64_t N, int64_t K);
 int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, int nterms, const double alpha[4],
                         const double beta[4], int64_t count, const ::qgemm_problem_t *probs, int force_class);

@@ -3,7 +3,7 @@
 For every size class of the tile table -- M and N buckets {8-16, 17-32,
 33-64, 65-512} and K buckets {8-64, 65-512} -- it builds a synthetic group of
 problems with sizes drawn log-uniformly inside the class, times one grouped
-launch with each of the five tile classes forced, and keeps the fastest.
+launch with each tile class forced, and keeps the fastest.
 The result is written as csrc/tile_table.inc (the table compiled into
 libqgemm.so; rebuild after running) together with the measured times.
 
@@ -83,7 +83,7 @@ def write_table(path, table, notes, count):
         f.write(f"// Classes: {cls} quaternions.\n")
         f.write("// Written by paper_1903_05575_amd/tune_tiles.py: fastest class of one grouped\n")
         f.write(f"// launch over {count} problems drawn log-uniformly inside each size class\n")
-        f.write("// (times in ms for classes 0..4):\n")
+        f.write(f"// (times in ms for classes 0..{len(_lib.TILE_CLASSES) - 1}):\n")
         for n in notes:
             f.write(f"//   {n}\n")
         f.write("static const unsigned char kTileTable[4][4][2] = {\n")

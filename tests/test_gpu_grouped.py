@@ -54,7 +54,7 @@ def test_grouped_small(gpu, opA, opB):
     plan.close()
 
 
-@pytest.mark.parametrize("cls", range(5))
+@pytest.mark.parametrize("cls", range(len(q.TILE_CLASSES)))
 def test_grouped_tile_classes(gpu, cls):
     probs = make_set(40, 1, 200, 100 + cls)
     al, be = np.array([1.0, 0, 0, 0]), np.array([0.5, 0, 0, 0])

@@ -97,7 +97,7 @@ def test_batched_plan_validation(L):
     probs[2].C = FAKE + 4
     rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
     assert rc == 2 and L.qgemm_last_invalid_arg() == 12 and L.qgemm_last_invalid_problem() == 2
-    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, 5)
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, 4)   # classes are 0..3
     assert rc == 1 and L.qgemm_last_invalid_arg() == 9
     probs[2].C = FAKE_B + 64                     # C of problem 2 inside its B
     rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
