@@ -33,10 +33,20 @@ bool ranges_overlap(const void *X, int64_t ldx, int64_t xrows, int64_t xcols, in
                     int64_t ldy, int64_t yrows, int64_t ycols, int64_t ybytes)
 {
     if (!X || !Y || xrows <= 0 || xcols <= 0 || yrows <= 0 || ycols <= 0) return false;
-    const uintptr_t x0 = reinterpret_cast<uintptr_t>(X), y0 = reinterpret_cast<uintptr_t>(Y);
-    const uintptr_t x1 = x0 + (uintptr_t)((ldx * (xcols - 1) + xrows) * xbytes);
-    const uintptr_t y1 = y0 + (uintptr_t)((ldy * (ycols - 1) + yrows) * ybytes);
+    const __int128 x0 = (__int128)reinterpret_cast<uintptr_t>(X), y0 = (__int128)reinterpret_cast<uintptr_t>(Y);
+    const __int128 x1 = x0 + ((__int128)ldx * (xcols - 1) + xrows) * xbytes;
+    const __int128 y1 = y0 + ((__int128)ldy * (ycols - 1) + yrows) * ybytes;
     return x0 < y1 && y0 < x1;
+}
+
+// Whether a rows x cols matrix with leading dimension ld and ebytes per
+// element spans at most 2^62 bytes, so that every element offset the kernels
+// form in 64 bits is exact.  (Larger leading dimensions are refused as
+// unsupported.)
+bool extent_fits(int64_t ld, int64_t rows, int64_t cols, int64_t ebytes)
+{
+    if (rows <= 0 || cols <= 0) return true;
+    return ((__int128)ld * (cols - 1) + rows) * ebytes <= ((__int128)1 << 62);
 }
 static_assert(QGEMM_DOT_WORK_DOUBLES >= 4 * qg::kDotParts, "dot workspace holds every partial sum");
 
@@ -67,6 +77,12 @@ qgemm_status_t validate(int opA, int opB, int64_t M, int64_t N, int64_t K, const
     if (ldc < (M > 1 ? M : 1)) return fail(QGEMM_ERR_INVALID_ARG, 13);
     if (M == 0 || N == 0) return QGEMM_OK;
     const bool reads_ab = K > 0 && !is_zero4(alpha);
+    {
+        const int64_t eb = ab_bytes ? ab_bytes : (int64_t)align;
+        if (reads_ab && !extent_fits(lda, rows_a, op_transposes(opA) ? M : K, eb)) return fail(QGEMM_ERR_UNSUPPORTED, 8);
+        if (reads_ab && !extent_fits(ldb, rows_b, op_transposes(opB) ? K : N, eb)) return fail(QGEMM_ERR_UNSUPPORTED, 10);
+        if (!extent_fits(ldc, M, N, (int64_t)align)) return fail(QGEMM_ERR_UNSUPPORTED, 13);
+    }
     if (reads_ab && !A) return fail(QGEMM_ERR_INVALID_ARG, 7);
     if (reads_ab && !B) return fail(QGEMM_ERR_INVALID_ARG, 9);
     if (!C) return fail(QGEMM_ERR_INVALID_ARG, 12);
@@ -184,6 +200,16 @@ qgemm_status_t backward_impl(int opA, int opB, int64_t M, int64_t N, int64_t K, 
     if (misaligned(dA)) return fail(QGEMM_ERR_MISALIGNED, 14);
     if (misaligned(dB)) return fail(QGEMM_ERR_MISALIGNED, 16);
     if (misaligned(dC0)) return fail(QGEMM_ERR_MISALIGNED, 18);
+    {
+        constexpr int64_t qb = 4 * sizeof(T);
+        const int64_t cols_a = op_transposes(opA) ? M : K, cols_b = op_transposes(opB) ? K : N;
+        if (!extent_fits(lda, rows_a, cols_a, qb)) return fail(QGEMM_ERR_UNSUPPORTED, 8);
+        if (!extent_fits(ldb, rows_b, cols_b, qb)) return fail(QGEMM_ERR_UNSUPPORTED, 10);
+        if (!extent_fits(ldg, M, N, qb)) return fail(QGEMM_ERR_UNSUPPORTED, 12);
+        if (dA && !extent_fits(ldda, rows_a, cols_a, qb)) return fail(QGEMM_ERR_UNSUPPORTED, 15);
+        if (dB && !extent_fits(lddb, rows_b, cols_b, qb)) return fail(QGEMM_ERR_UNSUPPORTED, 17);
+        if (dC0 && !extent_fits(lddc0, M, N, qb)) return fail(QGEMM_ERR_UNSUPPORTED, 19);
+    }
     {
         // every output is written while the other gradient launch may still read the inputs
         struct Span {
@@ -331,6 +357,9 @@ qgemm_status_t herk_impl(int uplo, int trans, int64_t N, int64_t K, double alpha
     if (!C) return fail(QGEMM_ERR_INVALID_ARG, 9);
     if (reads_a && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 6);
     if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 9);
+    if (reads_a && !extent_fits(lda, rows_a, trans == QGEMM_OP_N ? K : N, 4 * sizeof(T)))
+        return fail(QGEMM_ERR_UNSUPPORTED, 7);
+    if (!extent_fits(ldc, N, N, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 10);
     if (reads_a && ranges_overlap(C, ldc, N, N, 4 * sizeof(T), A, lda, rows_a, trans == QGEMM_OP_N ? K : N,
                                   4 * sizeof(T)))
         return fail(QGEMM_ERR_INVALID_ARG, 9);
@@ -383,6 +412,9 @@ qgemm_status_t trmm_impl(int side, int uplo, int trans, int diag, int64_t M, int
     if (reads_ab && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 8);
     if (reads_ab && (reinterpret_cast<uintptr_t>(B) % align)) return fail(QGEMM_ERR_MISALIGNED, 10);
     if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 12);
+    if (reads_ab && !extent_fits(lda, n, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 9);
+    if (reads_ab && !extent_fits(ldb, M, N, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 11);
+    if (!extent_fits(ldc, M, N, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 13);
     // C is written while A and B are still read by other tiles: no overlap
     if (reads_ab && (ranges_overlap(C, ldc, M, N, 4 * sizeof(T), A, lda, n, n, 4 * sizeof(T)) ||
                      ranges_overlap(C, ldc, M, N, 4 * sizeof(T), B, ldb, M, N, 4 * sizeof(T))))
@@ -425,6 +457,8 @@ qgemm_status_t axpy_impl(int64_t n, const double *alpha, const T *x, int64_t inc
     if (!y) return fail(QGEMM_ERR_INVALID_ARG, 5);
     if (reinterpret_cast<uintptr_t>(x) % align) return fail(QGEMM_ERR_MISALIGNED, 3);
     if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 5);
+    if (!extent_fits(incx, 1, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 4);
+    if (!extent_fits(incy, 1, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 6);
     if (!(x == y && incx == incy) && vec_overlap(x, n, incx, y, n, incy, 4 * sizeof(T)))
         return fail(QGEMM_ERR_INVALID_ARG, 5);
     return qg::launch_qaxpy<T>(n, alpha, x, incx, y, incy, stream) == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
@@ -449,6 +483,8 @@ qgemm_status_t dot_impl(int conj, int64_t n, const T *x, int64_t incx, const T *
         if (reinterpret_cast<uintptr_t>(x) % align) return fail(QGEMM_ERR_MISALIGNED, 3);
         if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 5);
         if (reinterpret_cast<uintptr_t>(work) % sizeof(double)) return fail(QGEMM_ERR_MISALIGNED, 8);
+        if (!extent_fits(incx, 1, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 4);
+        if (!extent_fits(incy, 1, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 6);
     }
     return qg::launch_qdot<T>(conj == 1, n, x, incx, y, incy, result, work, stream) == hipSuccess ? QGEMM_OK
                                                                                                 : QGEMM_ERR_HIP;
@@ -481,6 +517,9 @@ qgemm_status_t gemv_impl(int trans, int64_t M, int64_t N, const double *alpha, c
     if (!alpha_zero && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 5);
     if (!alpha_zero && (reinterpret_cast<uintptr_t>(x) % align)) return fail(QGEMM_ERR_MISALIGNED, 7);
     if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 10);
+    if (!alpha_zero && !extent_fits(lda, M, N, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 6);
+    if (!alpha_zero && !extent_fits(incx, 1, nx, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 8);
+    if (!extent_fits(incy, 1, ny, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 11);
     if (!alpha_zero && (vec_overlap(x, nx, incx, y, ny, incy, 4 * sizeof(T)) ||
                         ranges_overlap(A, lda, M, N, 4 * sizeof(T), y, incy, 1, ny, 4 * sizeof(T))))
         return fail(QGEMM_ERR_INVALID_ARG, 10);
@@ -619,6 +658,8 @@ qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, 
     if (reads_ab) {
         const int64_t ra = op_transposes(opA) ? K : M, ca = op_transposes(opA) ? M : K;
         const int64_t rb = op_transposes(opB) ? N : K, cb = op_transposes(opB) ? K : N;
+        if (!extent_fits(lda, ra, ca, 8 * typeA)) return fail(QGEMM_ERR_UNSUPPORTED, 10);
+        if (!extent_fits(ldb, rb, cb, 8 * typeB)) return fail(QGEMM_ERR_UNSUPPORTED, 12);
         if (ranges_overlap(C, ldc, M, N, 32, A, lda, ra, ca, 8 * typeA) ||
             ranges_overlap(C, ldc, M, N, 32, B, ldb, rb, cb, 8 * typeB))
             return fail(QGEMM_ERR_INVALID_ARG, 14);

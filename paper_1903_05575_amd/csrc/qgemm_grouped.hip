@@ -182,9 +182,20 @@ int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, i
         pl->s.alpha[i] = alpha[i];
         pl->s.beta[i] = beta[i];
     }
+    // count the tiles first: item indices and block starts are 32-bit on the device
+    int64_t total_tiles = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const ::qgemm_problem_t &q = probs[i];
+        if (q.M == 0 || q.N == 0) continue;
+        const int cls = force_class >= 0 ? force_class : grouped_tile_class(q.M, q.N, q.K);
+        total_tiles += ((q.M + kBM[cls] - 1) / kBM[cls]) * ((q.N + kBN[cls] - 1) / kBN[cls]);
+        if (total_tiles > 0x7fffffff) return QGEMM_ERR_UNSUPPORTED;
+    }
     std::vector<DevProblem> hp((size_t)count);
     std::vector<int4> items;
     std::vector<double> cost;
+    items.reserve((size_t)total_tiles);
+    cost.reserve((size_t)total_tiles);
     for (int64_t i = 0; i < count; ++i) {
         const ::qgemm_problem_t &q = probs[i];
         DevProblem &d = hp[(size_t)i];

@@ -300,3 +300,15 @@ def test_outputs_must_not_overlap_inputs(L):
     assert L.qgemm_backward_d(*args(G + 32, None, None)) == 1 and L.qgemm_last_invalid_arg() == 14
     assert L.qgemm_backward_d(*args(None, FAKE, None)) == 1 and L.qgemm_last_invalid_arg() == 16
     assert L.qgemm_backward_d(*args(0x60000, None, 0x60000 + 128)) == 1 and L.qgemm_last_invalid_arg() == 18
+
+
+def test_leading_dimensions_beyond_64bit_offsets_refused(L):
+    """A leading dimension whose matrix would span more than 2^62 bytes is
+    refused as unsupported (every offset the kernels form stays exact)."""
+    huge = 1 << 60
+    assert call_d(L, ldc=huge) == 5 and L.qgemm_last_invalid_arg() == 13
+    assert call_d(L, lda=huge) == 5 and L.qgemm_last_invalid_arg() == 8
+    assert L.qgemv_d(0, 4, 4, ONE, FAR_A, huge, FAR_B, 1, ONE, FAR_C, 1, None) == 5
+    assert L.qgemm_last_invalid_arg() == 6
+    assert L.qaxpy_d(4, ONE, FAR_A, huge, FAR_B, 1, None) == 5 and L.qgemm_last_invalid_arg() == 4
+    assert call_mixed(L, tA=4, tB=1, A=FAR_A, B=FAR_B, C=FAR_C, ldb=huge) == 5 and L.qgemm_last_invalid_arg() == 12
