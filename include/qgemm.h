@@ -37,7 +37,12 @@
  *     readable with qgemm_last_invalid_arg().
  *   - Requirements: M, N, K >= 0 and < 2^31; ld of a stored operand >=
  *     max(1, its stored rows); ldc >= max(1, M); base pointers aligned to one
- *     quaternion (32 bytes for double, 16 bytes for float).
+ *     quaternion (32 bytes for double, 16 bytes for float).  A matrix may
+ *     span at most 2^62 bytes ((ld (cols - 1) + rows) elements); the GEMM
+ *     tiles further address one K-tile of an operand with 32-bit offsets,
+ *     which bounds the leading dimension of a transposed A or of B with op
+ *     N / R (about 2^20 quaternions in double, 2^21 in float).  Beyond these
+ *     limits a call returns QGEMM_ERR_UNSUPPORTED.
  *   - Quick returns: M == 0 or N == 0 does nothing.  K == 0 or alpha == 0
  *     (all four components) computes C <- beta * C without reading A or B.
  *     beta == 0 (all four components) never reads C, so NaN/Inf there do not
