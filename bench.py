@@ -331,14 +331,17 @@ def variant_trmm(steps, warmup):
 def variant_mixed(steps, warmup):
     """Mixed-type GEMM qgemm_mixed_d, FP64 M = N = K = 8192 op N/N: quaternion
     x real (4 real multiply-adds per element product, 8 MNK flops) and complex
-    x quaternion (8 multiply-adds, 16 MNK flops); error on a 64 x 32 sample
-    against the oracle's qgemm_mixed."""
+    x quaternion (8 multiply-adds, 16 MNK flops), and quaternion x real with
+    float storage (qgemm_mixed_s, FP64 products); error on a 64 x 32 sample
+    against the oracle's qgemm_mixed on the same stored inputs."""
     import oracle
     n = 8192
     out = {}
-    for tA, tB, fpm, name in (("Q", "R", 8, "fp64_mixed_8192_quat_x_real"),
-                              ("Z", "Q", 16, "fp64_mixed_8192_complex_x_quat")):
+    for tA, tB, fpm, name, dt in (("Q", "R", 8, "fp64_mixed_8192_quat_x_real", np.float64),
+                                  ("Z", "Q", 16, "fp64_mixed_8192_complex_x_quat", np.float64),
+                                  ("Q", "R", 8, "fp32_storage_mixed_8192_quat_x_real", np.float32)):
         p = W.mixed_problem(W.BASE_SEED + 9 + fpm, tA, tB, n, n, n)
+        p = dict(p, A=p["A"].astype(dt), B=p["B"].astype(dt), C=p["C"].astype(dt))
         A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
         C0 = C.clone()
         _, ev = time_launches(lambda: q.qgemm_mixed(tA, tB, "N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),

@@ -261,6 +261,17 @@ qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, 
                              const double *alpha, const double *A, int64_t lda,
                              const double *B, int64_t ldb, const double *beta,
                              double *C, int64_t ldc, void *stream);
+/*
+ * qgemm_mixed_s -- as qgemm_mixed_d with float storage (A, B, C arrays of
+ * float; alignment 4, 8 or 16 bytes per element).  The elements are widened
+ * exactly to double as they are staged and the products are formed in FP64,
+ * so the only rounding beyond FP64 accumulation is the final store of C in
+ * float.  Both operands quaternion: same as qgemm_s with 6 products.
+ */
+qgemm_status_t qgemm_mixed_s(int typeA, int typeB, int opA, int opB, int64_t M, int64_t N, int64_t K,
+                             const double *alpha, const float *A, int64_t lda,
+                             const float *B, int64_t ldb, const double *beta,
+                             float *C, int64_t ldc, void *stream);
 
 /*
  * Level-1/2 operations (the quaternion BLAS-1/2 subset the paper's library

@@ -56,6 +56,8 @@ _SIGNATURES = {
     "qtrmm_s": ([_int, _int, _int, _int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _int, _vp], _int),
     "qgemm_mixed_d": ([_int, _int, _int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp],
                       _int),
+    "qgemm_mixed_s": ([_int, _int, _int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp],
+                      _int),
     "qaxpy_d": ([_i64, _dp, _vp, _i64, _vp, _i64, _vp], _int),
     "qaxpy_s": ([_i64, _dp, _vp, _i64, _vp, _i64, _vp], _int),
     "qdot_d": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp], _int),
@@ -346,20 +348,22 @@ TYPES = {"R": 1, "Z": 2, "Q": 4}
 
 
 def qgemm_mixed(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
-    """Mixed-type GEMM in binary64 (C-ABI qgemm_mixed_d): one of A, B real
-    ('R', tensor (cols, ld)) or complex ('Z', (cols, ld, 2)), the other
-    quaternion ('Q', (cols, ld, 4)); C quaternion."""
+    """Mixed-type GEMM (C-ABI qgemm_mixed_d for float64 tensors, qgemm_mixed_s
+    for float32): one of A, B real ('R', tensor (cols, ld)) or complex ('Z',
+    (cols, ld, 2)), the other quaternion ('Q', (cols, ld, 4)); C quaternion."""
+    dtype = C.dtype
     ra, ca = _stored(opA, M, K)
     rb, cb = _stored(opB, K, N)
     if M and N and K:
-        _check_storage(A, ra, ca, lda, torch.float64, "A", TYPES[typeA])
-        _check_storage(B, rb, cb, ldb, torch.float64, "B", TYPES[typeB])
-    _check_storage(C, M, N, ldc, torch.float64, "C")
+        _check_storage(A, ra, ca, lda, dtype, "A", TYPES[typeA])
+        _check_storage(B, rb, cb, ldb, dtype, "B", TYPES[typeB])
+    _check_storage(C, M, N, ldc, dtype, "C")
     pa, _ka = _q4(alpha)
     pb, _kb = _q4(beta)
-    rc = lib().qgemm_mixed_d(TYPES[typeA], TYPES[typeB], OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb,
-                             pb, _ptr(C), ldc, _stream(stream))
-    _raise(rc, "qgemm_mixed_d")
+    name = "qgemm_mixed_" + _suffix(dtype)
+    rc = getattr(lib(), name)(TYPES[typeA], TYPES[typeB], OPS[opA], OPS[opB], M, N, K, pa, _ptr(A), lda, _ptr(B), ldb,
+                              pb, _ptr(C), ldc, _stream(stream))
+    _raise(rc, name)
 
 
 DOT_WORK_DOUBLES = 4096      # QGEMM_DOT_WORK_DOUBLES of include/qgemm.h

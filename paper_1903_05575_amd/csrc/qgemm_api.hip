@@ -528,6 +528,69 @@ qgemm_status_t gemv_impl(int trans, int64_t M, int64_t N, const double *alpha, c
                : QGEMM_ERR_HIP;
 }
 
+// Mixed-type GEMM (one operand real or complex, the other quaternion) for
+// double (T = double) or float (T = float) storage; FP64 arithmetic either
+// way.  Argument numbering as in include/qgemm.h: 1 typeA, 2 typeB, then as
+// qgemm_d shifted by two.
+template <typename T>
+qgemm_status_t mixed_impl(int typeA, int typeB, int opA, int opB, int64_t M, int64_t N, int64_t K,
+                          const double *alpha, const T *A, int64_t lda, const T *B, int64_t ldb, const double *beta,
+                          T *C, int64_t ldc, hipStream_t stream)
+{
+    constexpr int64_t rb = sizeof(T);   // bytes of one real
+    g_bad_arg = 0;
+    auto valid_type = [](int t) { return t == QGEMM_REAL || t == QGEMM_COMPLEX || t == QGEMM_QUATERNION; };
+    if (!valid_type(typeA)) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    if (!valid_type(typeB)) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    if (typeA != QGEMM_QUATERNION && typeB != QGEMM_QUATERNION) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, rb, 0);
+    if (s != QGEMM_OK) return fail(s, g_bad_arg + 2);
+    if (M == 0 || N == 0) return QGEMM_OK;
+    const bool reads_ab = K > 0 && !is_zero4(alpha);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(A) % (uintptr_t)(rb * typeA))) return fail(QGEMM_ERR_MISALIGNED, 9);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(B) % (uintptr_t)(rb * typeB))) return fail(QGEMM_ERR_MISALIGNED, 11);
+    if (reinterpret_cast<uintptr_t>(C) % (uintptr_t)(4 * rb)) return fail(QGEMM_ERR_MISALIGNED, 14);
+    if (!extent_fits(ldc, M, N, 4 * rb)) return fail(QGEMM_ERR_UNSUPPORTED, 15);
+    if (reads_ab) {
+        const int64_t ra = op_transposes(opA) ? K : M, ca = op_transposes(opA) ? M : K;
+        const int64_t rbb = op_transposes(opB) ? N : K, cb = op_transposes(opB) ? K : N;
+        if (!extent_fits(lda, ra, ca, rb * typeA)) return fail(QGEMM_ERR_UNSUPPORTED, 10);
+        if (!extent_fits(ldb, rbb, cb, rb * typeB)) return fail(QGEMM_ERR_UNSUPPORTED, 12);
+        if (ranges_overlap(C, ldc, M, N, 4 * rb, A, lda, ra, ca, rb * typeA) ||
+            ranges_overlap(C, ldc, M, N, 4 * rb, B, ldb, rbb, cb, rb * typeB))
+            return fail(QGEMM_ERR_INVALID_ARG, 14);
+    }
+    if (typeA == QGEMM_QUATERNION && typeB == QGEMM_QUATERNION) {
+        if constexpr (sizeof(T) == 8) s = qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+        else s = qgemm_s(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 6, stream);
+        return s == QGEMM_OK ? s : fail(s, g_bad_arg + 2);
+    }
+    qg::MixedDesc d{};
+    const bool right = typeB == QGEMM_QUATERNION;   // quaternion is the right factor: out = C^T
+    d.f32 = sizeof(T) == 4;
+    d.right = right;
+    d.C = C;
+    d.ldc = ldc;
+    d.K = (int)K;
+    if (!right) {
+        d.X = A; d.ldx = lda; d.P = (int)M; d.xt = op_transposes(opA); d.conjX = op_conjugates(opA);
+        d.Y = B; d.ldy = ldb; d.Q = (int)N; d.yt = op_transposes(opB); d.conjY = typeB == QGEMM_COMPLEX && op_conjugates(opB);
+        d.kc = typeB;
+    } else {
+        d.X = B; d.ldx = ldb; d.P = (int)N; d.xt = !op_transposes(opB); d.conjX = op_conjugates(opB);
+        d.Y = A; d.ldy = lda; d.Q = (int)M; d.yt = !op_transposes(opA); d.conjY = typeA == QGEMM_COMPLEX && op_conjugates(opA);
+        d.kc = typeA;
+    }
+    for (int i = 0; i < 4; ++i) {
+        d.alpha[i] = alpha[i];
+        d.beta[i] = beta[i];
+    }
+    if (!qg::mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc, (int)rb))
+        return fail(QGEMM_ERR_UNSUPPORTED, right ? 12 : 10);
+    if (qg::launch_qgemm_mixed_f64(d, stream) != hipSuccess) return QGEMM_ERR_HIP;
+    return QGEMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -643,53 +706,16 @@ qgemm_status_t qgemm_mixed_d(int typeA, int typeB, int opA, int opB, int64_t M, 
                              const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                              const double *beta, double *C, int64_t ldc, void *stream)
 {
-    g_bad_arg = 0;
-    auto valid_type = [](int t) { return t == QGEMM_REAL || t == QGEMM_COMPLEX || t == QGEMM_QUATERNION; };
-    if (!valid_type(typeA)) return fail(QGEMM_ERR_INVALID_ARG, 1);
-    if (!valid_type(typeB)) return fail(QGEMM_ERR_INVALID_ARG, 2);
-    if (typeA != QGEMM_QUATERNION && typeB != QGEMM_QUATERNION) return fail(QGEMM_ERR_INVALID_ARG, 2);
-    qgemm_status_t s = validate(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 8, 0);
-    if (s != QGEMM_OK) return fail(s, g_bad_arg + 2);
-    if (M == 0 || N == 0) return QGEMM_OK;
-    const bool reads_ab = K > 0 && !is_zero4(alpha);
-    if (reads_ab && (reinterpret_cast<uintptr_t>(A) % (8u * typeA))) return fail(QGEMM_ERR_MISALIGNED, 9);
-    if (reads_ab && (reinterpret_cast<uintptr_t>(B) % (8u * typeB))) return fail(QGEMM_ERR_MISALIGNED, 11);
-    if (reinterpret_cast<uintptr_t>(C) % 32u) return fail(QGEMM_ERR_MISALIGNED, 14);
-    if (reads_ab) {
-        const int64_t ra = op_transposes(opA) ? K : M, ca = op_transposes(opA) ? M : K;
-        const int64_t rb = op_transposes(opB) ? N : K, cb = op_transposes(opB) ? K : N;
-        if (!extent_fits(lda, ra, ca, 8 * typeA)) return fail(QGEMM_ERR_UNSUPPORTED, 10);
-        if (!extent_fits(ldb, rb, cb, 8 * typeB)) return fail(QGEMM_ERR_UNSUPPORTED, 12);
-        if (ranges_overlap(C, ldc, M, N, 32, A, lda, ra, ca, 8 * typeA) ||
-            ranges_overlap(C, ldc, M, N, 32, B, ldb, rb, cb, 8 * typeB))
-            return fail(QGEMM_ERR_INVALID_ARG, 14);
-    }
-    if (typeA == QGEMM_QUATERNION && typeB == QGEMM_QUATERNION) {
-        s = qgemm_d(opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
-        return s == QGEMM_OK ? s : fail(s, g_bad_arg + 2);
-    }
-    qg::MixedDesc d{};
-    const bool right = typeB == QGEMM_QUATERNION;   // quaternion is the right factor: out = C^T
-    d.right = right;
-    d.C = C;
-    d.ldc = ldc;
-    d.K = (int)K;
-    if (!right) {
-        d.X = A; d.ldx = lda; d.P = (int)M; d.xt = op_transposes(opA); d.conjX = op_conjugates(opA);
-        d.Y = B; d.ldy = ldb; d.Q = (int)N; d.yt = op_transposes(opB); d.conjY = typeB == QGEMM_COMPLEX && op_conjugates(opB);
-        d.kc = typeB;
-    } else {
-        d.X = B; d.ldx = ldb; d.P = (int)N; d.xt = !op_transposes(opB); d.conjX = op_conjugates(opB);
-        d.Y = A; d.ldy = lda; d.Q = (int)M; d.yt = !op_transposes(opA); d.conjY = typeA == QGEMM_COMPLEX && op_conjugates(opA);
-        d.kc = typeA;
-    }
-    for (int i = 0; i < 4; ++i) {
-        d.alpha[i] = alpha[i];
-        d.beta[i] = beta[i];
-    }
-    if (!qg::mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc)) return fail(QGEMM_ERR_UNSUPPORTED, right ? 12 : 10);
-    if (qg::launch_qgemm_mixed_f64(d, static_cast<hipStream_t>(stream)) != hipSuccess) return QGEMM_ERR_HIP;
-    return QGEMM_OK;
+    return mixed_impl<double>(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                              static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qgemm_mixed_s(int typeA, int typeB, int opA, int opB, int64_t M, int64_t N, int64_t K,
+                             const double *alpha, const float *A, int64_t lda, const float *B, int64_t ldb,
+                             const double *beta, float *C, int64_t ldc, void *stream)
+{
+    return mixed_impl<float>(typeA, typeB, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                             static_cast<hipStream_t>(stream));
 }
 
 qgemm_status_t qaxpy_d(int64_t n, const double *alpha, const double *x, int64_t incx, double *y, int64_t incy,

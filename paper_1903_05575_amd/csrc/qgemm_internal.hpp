@@ -109,9 +109,10 @@ inline bool split_ld_supported(int64_t lda, int64_t ldb, bool ta, bool tb)
 // (kc = 2, re/im interleaved) operand (K x Q after its op); out is C, or C^T
 // when `right` (the quaternion is the right factor of C = op(A) op(B)).
 struct MixedDesc {
-    const double *X;
-    const double *Y;
-    double *C;
+    const void *X;         // double or float (f32), as all three arrays
+    const void *Y;
+    void *C;
+    bool f32;              // storage is float (arithmetic is FP64 either way)
     int64_t ldx, ldy, ldc;
     int P, Q, K;
     int kc;
@@ -122,7 +123,7 @@ struct MixedDesc {
     double alpha[4];
     double beta[4];
 };
-bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc);
+bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc, int real_bytes);
 hipError_t launch_qgemm_mixed_f64(const MixedDesc &d, hipStream_t stream);
 
 // Level-1/2 launches (qblas_l12.hip).  The dot product uses at most

@@ -39,42 +39,64 @@
 //   Y stage: [kappa * KC + s][q], row pitch BQ + 1
 #include "qgemm_internal.hpp"
 
-#include <type_traits>
-
 namespace qg {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BP = 32, BQ = 128, NT = 256, STEPS = 4;
 constexpr int XP = 4 * BP + 4;      // doubles per kappa row of the X stage
 constexpr int YP = BQ + 1;          // doubles per row of the Y stage
 constexpr unsigned kOob = 0x80000000u;
 
-template <int KC>
+// Storage type T (double or float): operands are read in T and widened
+// exactly to double while staged, so the LDS tiles, the MFMAs and the
+// epilogue arithmetic are FP64 for both; C is stored in T.
+template <int KC, typename T>
 struct Shape {
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
     static constexpr int STAGE = X_STAGE + Y_STAGE;
-    static constexpr int X_CH = BP * BK * 2 / NT;              // 16-byte halves of X per thread
+    static constexpr int XPER = sizeof(T) == 8 ? 2 : 1;       // 16-byte loads per quaternion of X
+    static constexpr int X_CH = BP * BK * XPER / NT;           // 16-byte loads of X per thread
     static constexpr int Y_EL = BK * BQ / NT;                  // Y elements per thread
+    static constexpr int YBYTES = KC * (int)sizeof(T);         // bytes of one Y element
     static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
-    static_assert(X_CH * NT == BP * BK * 2, "X tile must split evenly");
+    static_assert(X_CH * NT == BP * BK * XPER, "X tile must split evenly");
     static_assert(Y_EL * NT == BK * BQ, "Y tile must split evenly");
 };
+
+// raw register type of one Y element of `bytes` bytes
+template <int bytes>
+struct RawY;
+template <>
+struct RawY<4> { typedef unsigned type; };
+template <>
+struct RawY<8> { typedef u32x2 type; };
+template <>
+struct RawY<16> { typedef u32x4 type; };
 
 __device__ __forceinline__ double flip(double v, bool neg)
 {
     return __longlong_as_double(__double_as_longlong(v) ^ (neg ? (long long)0x8000000000000000ull : 0ll));
 }
 
-template <int KC, bool RIGHT, bool XT, bool YT>
+template <typename T, int KC, bool RIGHT, bool XT, bool YT>
 __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int tiles_p, int tiles_q, int nk)
 {
-    using S = Shape<KC>;
+    using S = Shape<KC, T>;
     constexpr int BK = S::BK;
+    constexpr int XPER = S::XPER;
+    typedef typename RawY<S::YBYTES>::type YRaw;
+    const T *X = static_cast<const T *>(p.X);
+    const T *Y = static_cast<const T *>(p.Y);
+    T *Cp = static_cast<T *>(p.C);
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -103,15 +125,16 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
 #pragma unroll
         for (int n = 0; n < 8; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
 
-    d2 rx[S::X_CH];
-    typedef typename std::conditional<KC == 1, double, d2>::type YT_t;
-    YT_t ry[S::Y_EL];
+    u32x4 rx[S::X_CH];
+    YRaw ry[S::Y_EL];
 
+    // X load i: half `half` (double) or all (float) of quaternion (pp, ka)
     auto x_slot = [&](int i, int &pp, int &ka, int &half) {
         const int q = tid + NT * i;
-        half = q & 1;
-        if (!XT) { pp = (q >> 1) % BP; ka = (q >> 1) / BP; }
-        else     { ka = (q >> 1) % BK; pp = (q >> 1) / BK; }
+        half = XPER == 2 ? (q & 1) : 0;
+        const int e = XPER == 2 ? (q >> 1) : q;
+        if (!XT) { pp = e % BP; ka = e / BP; }
+        else     { ka = e % BK; pp = e / BK; }
     };
     auto y_slot = [&](int i, int &ka, int &qq) {
         const int e = tid + NT * i;
@@ -122,8 +145,8 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
     auto load_tile = [&](int kt) {
         const int k0 = kt * BK;
         const int krem = p.K - k0;
-        const double *Xb = p.X + 4 * (XT ? ((int64_t)p0 * p.ldx + k0) : ((int64_t)k0 * p.ldx + p0));
-        const double *Yb = p.Y + KC * (YT ? ((int64_t)k0 * p.ldy + q0) : ((int64_t)q0 * p.ldy + k0));
+        const T *Xb = X + 4 * (XT ? ((int64_t)p0 * p.ldx + k0) : ((int64_t)k0 * p.ldx + p0));
+        const T *Yb = Y + KC * (YT ? ((int64_t)k0 * p.ldy + q0) : ((int64_t)q0 * p.ldy + k0));
         const __amdgpu_buffer_rsrc_t rX = __builtin_amdgcn_make_buffer_rsrc((void *)Xb, (short)0, 0x7fffffff, 0x00020000);
         const __amdgpu_buffer_rsrc_t rY = __builtin_amdgcn_make_buffer_rsrc((void *)Yb, (short)0, 0x7fffffff, 0x00020000);
 #pragma unroll
@@ -132,7 +155,7 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
             x_slot(i, pp, ka, half);
             const unsigned e = XT ? (unsigned)pp * (unsigned)p.ldx + ka : (unsigned)ka * (unsigned)p.ldx + pp;
             const bool ok = p0 + pp < p.P && ka < krem;
-            rx[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rX, ok ? 32u * e + 16u * half : kOob, 0, 0));
+            rx[i] = __builtin_amdgcn_raw_buffer_load_b128(rX, ok ? (unsigned)(4 * sizeof(T)) * e + 16u * half : kOob, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < S::Y_EL; ++i) {
@@ -140,9 +163,10 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
             y_slot(i, ka, qq);
             const unsigned e = YT ? (unsigned)ka * (unsigned)p.ldy + qq : (unsigned)qq * (unsigned)p.ldy + ka;
             const bool ok = q0 + qq < p.Q && ka < krem;
-            const unsigned o = ok ? (unsigned)(8 * KC) * e : kOob;
-            if constexpr (KC == 1) ry[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rY, o, 0, 0));
-            else ry[i] = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(rY, o, 0, 0));
+            const unsigned o = ok ? (unsigned)S::YBYTES * e : kOob;
+            if constexpr (S::YBYTES == 4) ry[i] = __builtin_amdgcn_raw_buffer_load_b32(rY, o, 0, 0);
+            else if constexpr (S::YBYTES == 8) ry[i] = __builtin_amdgcn_raw_buffer_load_b64(rY, o, 0, 0);
+            else ry[i] = __builtin_amdgcn_raw_buffer_load_b128(rY, o, 0, 0);
         }
     };
 
@@ -152,17 +176,34 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
         for (int i = 0; i < S::X_CH; ++i) {
             int pp, ka, half;
             x_slot(i, pp, ka, half);
-            *reinterpret_cast<d2 *>(Xs + ka * XP + pp * 4 + 2 * half) = rx[i];
+            if constexpr (XPER == 2) {
+                *reinterpret_cast<d2 *>(Xs + ka * XP + pp * 4 + 2 * half) = __builtin_bit_cast(d2, rx[i]);
+            } else {
+                const f4 v = __builtin_bit_cast(f4, rx[i]);
+                *reinterpret_cast<d2 *>(Xs + ka * XP + pp * 4) = (d2){(double)v.x, (double)v.y};
+                *reinterpret_cast<d2 *>(Xs + ka * XP + pp * 4 + 2) = (d2){(double)v.z, (double)v.w};
+            }
         }
 #pragma unroll
         for (int i = 0; i < S::Y_EL; ++i) {
             int ka, qq;
             y_slot(i, ka, qq);
             if constexpr (KC == 1) {
-                Ys[ka * YP + qq] = ry[i];
+                double v;
+                if constexpr (sizeof(T) == 8) v = __builtin_bit_cast(double, ry[i]);
+                else v = (double)__builtin_bit_cast(float, ry[i]);
+                Ys[ka * YP + qq] = v;
             } else {
-                Ys[(2 * ka) * YP + qq] = ry[i].x;
-                Ys[(2 * ka + 1) * YP + qq] = ry[i].y;
+                double re, im;
+                if constexpr (sizeof(T) == 8) {
+                    const d2 z = __builtin_bit_cast(d2, ry[i]);
+                    re = z.x; im = z.y;
+                } else {
+                    const f2 z = __builtin_bit_cast(f2, ry[i]);
+                    re = z.x; im = z.y;
+                }
+                Ys[(2 * ka) * YP + qq] = re;
+                Ys[(2 * ka + 1) * YP + qq] = im;
             }
         }
     };
@@ -225,25 +266,35 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
             const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
             double o[4];
             qmul(p.alpha, v, o);
-            d2 *dst = reinterpret_cast<d2 *>(p.C + 4 * ((int64_t)nu * p.ldc + mu));
+            T *dst = Cp + 4 * ((int64_t)nu * p.ldc + mu);
             if (!beta_zero) {
-                const d2 c0 = dst[0], c1 = dst[1];
-                const double cq[4] = {c0.x, c0.y, c1.x, c1.y};
+                double cq[4];
+                if constexpr (sizeof(T) == 8) {
+                    const d2 c0 = reinterpret_cast<const d2 *>(dst)[0], c1 = reinterpret_cast<const d2 *>(dst)[1];
+                    cq[0] = c0.x; cq[1] = c0.y; cq[2] = c1.x; cq[3] = c1.y;
+                } else {
+                    const f4 c = *reinterpret_cast<const f4 *>(dst);
+                    cq[0] = c.x; cq[1] = c.y; cq[2] = c.z; cq[3] = c.w;
+                }
                 double u[4];
                 qmul(p.beta, cq, u);
                 o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
             }
-            dst[0] = (d2){o[0], o[1]};
-            dst[1] = (d2){o[2], o[3]};
+            if constexpr (sizeof(T) == 8) {
+                reinterpret_cast<d2 *>(dst)[0] = (d2){o[0], o[1]};
+                reinterpret_cast<d2 *>(dst)[1] = (d2){o[2], o[3]};
+            } else {
+                *reinterpret_cast<f4 *>(dst) = (f4){(float)o[0], (float)o[1], (float)o[2], (float)o[3]};
+            }
         }
     }
 }
 
-template <int KC, bool RIGHT, bool XT, bool YT>
+template <typename T, int KC, bool RIGHT, bool XT, bool YT>
 hipError_t launch_t(const MixedDesc &d, hipStream_t stream)
 {
-    using S = Shape<KC>;
-    auto kern = &qgemm_mixed_f64_kernel<KC, RIGHT, XT, YT>;
+    using S = Shape<KC, T>;
+    auto kern = &qgemm_mixed_f64_kernel<T, KC, RIGHT, XT, YT>;
     static std::atomic<uint64_t> lds_set{0};
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(kern), (int)S::LDS_BYTES, lds_set);
     if (e != hipSuccess) return e;
@@ -258,30 +309,36 @@ hipError_t launch_t(const MixedDesc &d, hipStream_t stream)
     return hipGetLastError();
 }
 
-template <int KC, bool RIGHT>
+template <typename T, int KC, bool RIGHT>
 hipError_t launch_layouts(const MixedDesc &d, hipStream_t s)
 {
-    if (d.xt) return d.yt ? launch_t<KC, RIGHT, true, true>(d, s) : launch_t<KC, RIGHT, true, false>(d, s);
-    return d.yt ? launch_t<KC, RIGHT, false, true>(d, s) : launch_t<KC, RIGHT, false, false>(d, s);
+    if (d.xt) return d.yt ? launch_t<T, KC, RIGHT, true, true>(d, s) : launch_t<T, KC, RIGHT, true, false>(d, s);
+    return d.yt ? launch_t<T, KC, RIGHT, false, true>(d, s) : launch_t<T, KC, RIGHT, false, false>(d, s);
+}
+
+template <typename T>
+hipError_t launch_kinds(const MixedDesc &d, hipStream_t s)
+{
+    if (d.kc == 1) return d.right ? launch_layouts<T, 1, true>(d, s) : launch_layouts<T, 1, false>(d, s);
+    if (d.kc == 2) return d.right ? launch_layouts<T, 2, true>(d, s) : launch_layouts<T, 2, false>(d, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc)
+bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc, int real_bytes)
 {
     const int64_t lim = (int64_t)1 << 31;
     const int bk = STEPS * 4 / kc;
-    const int64_t fx = 32 * (xt ? ((int64_t)BP * ldx + bk) : ((int64_t)bk * ldx + BP));
-    const int64_t fy = 8 * kc * (yt ? ((int64_t)bk * ldy + BQ) : ((int64_t)BQ * ldy + bk));
+    const int64_t fx = 4 * real_bytes * (xt ? ((int64_t)BP * ldx + bk) : ((int64_t)bk * ldx + BP));
+    const int64_t fy = kc * real_bytes * (yt ? ((int64_t)bk * ldy + BQ) : ((int64_t)BQ * ldy + bk));
     return fx < lim && fy < lim;
 }
 
 hipError_t launch_qgemm_mixed_f64(const MixedDesc &d, hipStream_t stream)
 {
-    if (!mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc)) return hipErrorInvalidValue;
-    if (d.kc == 1) return d.right ? launch_layouts<1, true>(d, stream) : launch_layouts<1, false>(d, stream);
-    if (d.kc == 2) return d.right ? launch_layouts<2, true>(d, stream) : launch_layouts<2, false>(d, stream);
-    return hipErrorInvalidValue;
+    if (!mixed_ld_supported(d.ldx, d.ldy, d.xt, d.yt, d.kc, d.f32 ? 4 : 8)) return hipErrorInvalidValue;
+    return d.f32 ? launch_kinds<float>(d, stream) : launch_kinds<double>(d, stream);
 }
 
 }  // namespace qg

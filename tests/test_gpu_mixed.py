@@ -73,3 +73,30 @@ def test_mixed_quaternion_pair_is_qgemm(gpu):
     q.qgemm_mixed("Q", "Q", "T", "C", 100, 90, 80, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], Cm, p["ldc"])
     q.qgemm_d("T", "C", 100, 90, 80, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], Cg, p["ldc"])
     np.testing.assert_array_equal(host(Cm), host(Cg))
+
+
+def as32(p):
+    return dict(p, A=p["A"].astype(np.float32), B=p["B"].astype(np.float32), C=p["C"].astype(np.float32))
+
+
+@pytest.mark.parametrize("tA,tB", PAIRS)
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C"), ("C", "R"), ("R", "T")])
+def test_mixed_f32_storage(gpu, tA, tB, opA, opB):
+    """qgemm_mixed_s: float storage, FP64 products; against the oracle on the
+    same float inputs the only error is the final rounding of C to float."""
+    p = as32(W.mixed_problem(1190 + PAIRS.index((tA, tB)) * 4 + [("N", "N"), ("T", "C"), ("C", "R"), ("R", "T")].index(
+        (opA, opB)), tA, tB, 150, 97, 133, opA, opB, dist="normal", pad=1))
+    M, N = p["M"], p["N"]
+    got, ref = run(p), want(p)
+    assert got.dtype == np.float32
+    assert relfro(logical(got, M, N), logical(ref, M, N)) <= 1e-7
+    np.testing.assert_array_equal(got[:, M:], p["C"][:, M:])
+
+
+def test_mixed_f32_quaternion_pair_is_qgemm_s(gpu):
+    p = W.gemm_problem(1199, 100, 90, 80, "N", "C", dtype=np.float32)
+    Cm, Cg = dev(p["C"]), dev(p["C"])
+    A, B = dev(p["A"]), dev(p["B"])
+    q.qgemm_mixed("Q", "Q", "N", "C", 100, 90, 80, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], Cm, p["ldc"])
+    q.qgemm_s("N", "C", 100, 90, 80, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], Cg, p["ldc"])
+    np.testing.assert_array_equal(host(Cm), host(Cg))

@@ -312,3 +312,13 @@ def test_leading_dimensions_beyond_64bit_offsets_refused(L):
     assert L.qgemm_last_invalid_arg() == 6
     assert L.qaxpy_d(4, ONE, FAR_A, huge, FAR_B, 1, None) == 5 and L.qgemm_last_invalid_arg() == 4
     assert call_mixed(L, tA=4, tB=1, A=FAR_A, B=FAR_B, C=FAR_C, ldb=huge) == 5 and L.qgemm_last_invalid_arg() == 12
+
+
+def test_validation_mixed_s(L):
+    """qgemm_mixed_s: float storage, element alignment 4 / 8 / 16 bytes."""
+    args = lambda tA, tB, A, B, C: (tA, tB, 0, 0, 4, 4, 4, ONE, A, 4, B, 4, ONE, C, 4, None)
+    assert L.qgemm_mixed_s(*args(4, 1, FAR_A + 8, FAR_B, FAR_C)) == 2 and L.qgemm_last_invalid_arg() == 9
+    assert L.qgemm_mixed_s(*args(4, 1, FAR_A, FAR_B + 2, FAR_C)) == 2 and L.qgemm_last_invalid_arg() == 11
+    assert L.qgemm_mixed_s(*args(2, 4, FAR_A + 4, FAR_B, FAR_C)) == 2 and L.qgemm_last_invalid_arg() == 9
+    assert L.qgemm_mixed_s(*args(4, 1, FAR_A, FAR_B, FAR_C + 8)) == 2 and L.qgemm_last_invalid_arg() == 14
+    assert L.qgemm_mixed_s(*args(1, 1, FAR_A, FAR_B, FAR_C)) == 1 and L.qgemm_last_invalid_arg() == 2
