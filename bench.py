@@ -21,6 +21,7 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    plus vendor context (rocBLAS ZGEMM / DGEMM on embeddings).
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
+    python bench.py --probe-ops         one launch per op pair at 2048, for per-kernel counters
     python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed|blas12|shard|context
                                                    one part, no CPU baseline
     python bench.py --sweep                        FP64 sizes 1024..8192 x op pairs, one line each
@@ -491,21 +492,47 @@ def variant_context(steps, warmup):
 def sweep(steps, warmup):
     """FP64 qgemm_d over M = N = K in 1024..8192 and every op pair of N, T, C:
     one JSON line per case (event time per launch and effective TFLOP/s);
-    sizes up to 2048 are timed over at least 50 launches after 10."""
+    sizes up to 2048 are timed over at least 50 launches after 10, in three
+    such windows of which the median is reported (a one-off clock change
+    during a sub-millisecond window would otherwise decide the figure)."""
     for n in W.SWEEP_SIZES:
         for opA, opB in W.OP_PAIRS:
             p = W.gemm_sweep(n, opA, opB)
             A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
             # short launches need more of them for steady clocks
-            st, wu = (max(steps, 50), max(warmup, 10)) if n <= 2048 else (steps, warmup)
-            _, ev = time_launches(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
-                                                    p["beta"], C, p["ldc"]), st, wu)
+            st, wu, win = (max(steps, 50), max(warmup, 10), 3) if n <= 2048 else (steps, warmup, 1)
+            evs = [time_launches(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
+                                                   p["beta"], C, p["ldc"]), st, wu)[1] for _ in range(win)]
+            ev = sorted(evs)[len(evs) // 2]
             fl = q.flops(n, n, n)
             print(json.dumps({"sweep": f"{n} {opA}/{opB}", "ms": round(ev, 3),
                               "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
                               "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4)}), flush=True)
             del A, B, C
             torch.cuda.empty_cache()
+
+
+def probe_ops(n=2048):
+    """One launch per op pair of qgemm_d and qgemm_s, and of qgemm_mixed_d for
+    each type pair (op N/N and T/T), at M = N = K = n: a short program for
+    per-kernel counter runs (LDS bank conflicts by op pair)."""
+    widths = {"R": 1, "Z": 2, "Q": 4}
+    for dt, fn in ((torch.float64, q.qgemm_d), (torch.float32, q.qgemm_s)):
+        A = torch.rand(n * n * 4, dtype=dt, device="cuda")
+        B = torch.rand(n * n * 4, dtype=dt, device="cuda")
+        C = torch.zeros(n * n * 4, dtype=dt, device="cuda")
+        for oa, ob in W.OP_PAIRS:
+            fn(oa, ob, n, n, n, (1, 0, 0, 0), A, n, B, n, (0, 0, 0, 0), C, n)
+            torch.cuda.synchronize()
+            log(f"{'qgemm_d' if dt == torch.float64 else 'qgemm_s'} {oa}/{ob} n={n}")
+    for ta, tb in (("Q", "R"), ("R", "Q"), ("Z", "Q"), ("Q", "Z")):
+        for oa, ob in (("N", "N"), ("T", "T")):
+            A = torch.rand(n * n * widths[ta], dtype=torch.float64, device="cuda")
+            B = torch.rand(n * n * widths[tb], dtype=torch.float64, device="cuda")
+            C = torch.zeros(n * n * 4, dtype=torch.float64, device="cuda")
+            q.qgemm_mixed(ta, tb, oa, ob, n, n, n, (1, 0, 0, 0), A, n, B, n, (0, 0, 0, 0), C, n)
+            torch.cuda.synchronize()
+            log(f"qgemm_mixed {ta}x{tb} {oa}/{ob} n={n}")
 
 
 def calibrate_copy():
@@ -528,6 +555,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--probe-ops", action="store_true", help="one launch per op pair at 2048 (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="time the FP64 size x op-pair sweep, one line per case")
     ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12", "shard",
                                        "context"],
@@ -543,6 +571,9 @@ def main():
     q.lib()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.probe_ops:
+        probe_ops()
         return
     if args.sweep:
         sweep(args.steps, args.warmup)

@@ -37,7 +37,9 @@
 // advances in tiles of BK quaternions through one or two LDS stages.
 // LDS (32-bit words): per stage, A as [piece][row][kappa][2 words] and B as
 // [piece][column][kappa][2 words], row pitch 2 BK + 4 words.  The 16-byte pad
-// spreads the 16-byte fragment reads of consecutive rows over the banks.
+// spreads the 16-byte fragment reads of consecutive rows over the banks, and
+// the staging threads are laid out so that their 8-byte writes do not collide
+// either (slot_coords): no LDS bank conflicts for any op pair.
 #pragma once
 
 #include "qgemm_internal.hpp"
@@ -145,6 +147,29 @@ struct Tile {
     static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA kappa step");
 };
 
+// Staging slot qd of a ROWS x BK tile -> (row, kappa).  Every group of 16
+// lanes writes 8-byte words that fall on 32 distinct banks of the row pitch
+// 2 BK + 4 words: with the operand contiguous along the row index (ROW_FAST)
+// the group takes 8 rows x 2 kappa; contiguous along kappa, one row of 16
+// kappa (BK = 16) or two rows 4 apart of 8 kappa (BK = 8, 80 bytes x 4 rows
+// = half the banks).  Global reads stay in runs of 8 or 16 quaternions.
+template <int ROWS, int BK, bool ROW_FAST>
+__device__ __forceinline__ void slot_coords(int qd, int &row, int &ka)
+{
+    static_assert(ROWS % 8 == 0 && (BK == 8 || BK == 16), "staging slot layout");
+    const int lo = qd & 15, hi = qd >> 4;
+    if constexpr (ROW_FAST) {
+        row = (hi % (ROWS / 8)) * 8 + (lo & 7);
+        ka = (hi / (ROWS / 8)) * 2 + (lo >> 3);
+    } else if constexpr (BK == 8) {
+        ka = lo & 7;
+        row = (lo >> 3) * 4 + (hi & 3) + 8 * (hi >> 2);
+    } else {
+        ka = lo;
+        row = hi;
+    }
+}
+
 // Compute the BM x BN output tile at (m0, n0) of problem p and write it.
 // nk = number of K-tiles to walk (0 when alpha == 0).  `lds` must hold
 // TL::LDS_BYTES (STAGES = 2) or TL::LDS_BYTES_1 (STAGES = 1).  Every thread of
@@ -201,8 +226,7 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
 #pragma unroll
     for (int i = 0; i < TL::A_Q; ++i) {
         const int qd = tid + NT * i;
-        if (!TA) { a_r[i] = qd % BM; a_k[i] = qd / BM; }     // stored contiguous along mu
-        else     { a_k[i] = qd % BK; a_r[i] = qd / BK; }     // stored contiguous along kappa
+        slot_coords<BM, BK, !TA>(qd, a_r[i], a_k[i]);
         a_off[i] = m0 + a_r[i] < p.M ? 16u * (TA ? (unsigned)a_r[i] * (unsigned)p.lda + a_k[i]
                                                  : (unsigned)a_k[i] * (unsigned)p.lda + a_r[i])
                                      : kOob;
@@ -210,8 +234,7 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
 #pragma unroll
     for (int i = 0; i < TL::B_Q; ++i) {
         const int qd = tid + NT * i;
-        if (!TB) { b_k[i] = qd % BK; b_c[i] = qd / BK; }
-        else     { b_c[i] = qd % BN; b_k[i] = qd / BN; }
+        slot_coords<BN, BK, TB>(qd, b_c[i], b_k[i]);
         b_off[i] = n0 + b_c[i] < p.N ? 16u * (TB ? (unsigned)b_k[i] * (unsigned)p.ldb + b_c[i]
                                                  : (unsigned)b_c[i] * (unsigned)p.ldb + b_k[i])
                                      : kOob;
@@ -381,20 +404,39 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
     }
     flush();
 
-    // epilogue: a lane holds quaternions (registers 4j..4j+3) of rows 2j + lane/32 of each 8-row block
+    // epilogue: a lane holds quaternions (registers 4j..4j+3) of rows 2j + lane/32 of each 8-row block.
+    // The old C values of a group of outputs are all requested before the first of them is written, so
+    // their latencies overlap (a read after a write to the same array is not reordered by the compiler).
     const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
+    auto out_index = [&](int m, int n, int j, int &mu, int &nu, int64_t &e) -> bool {
+        mu = m0 + a_row - (fi >> 2) + 8 * m + 2 * j + fg;
+        nu = n0 + b_row + 32 * n;
+        if (mu >= p.M || nu >= p.N) return false;
+        if (p.uplo != 0 && (p.uplo == 1 ? mu < nu : mu > nu)) return false;
+        e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
+        return true;
+    };
+    if constexpr (C64) {
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+        for (int m = 0; m < MB; ++m)
 #pragma unroll
-        for (int n = 0; n < NB; ++n)
+            for (int n = 0; n < NB; ++n) {
+                double cold[4][4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int mu = m0 + a_row - (fi >> 2) + 8 * m + 2 * j + fg;
-                const int nu = n0 + b_row + 32 * n;
-                if (mu >= p.M || nu >= p.N) continue;
-                if (p.uplo != 0 && (p.uplo == 1 ? mu < nu : mu > nu)) continue;
-                const int64_t e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
-                if constexpr (C64) {
+                for (int j = 0; j < 4; ++j) {
+                    int mu, nu;
+                    int64_t e = 0;
+                    cold[j][0] = cold[j][1] = cold[j][2] = cold[j][3] = 0.0;
+                    if (!beta_zero && out_index(m, n, j, mu, nu, e)) {
+                        const double *src = c64 + 4 * e;
+                        cold[j][0] = src[0]; cold[j][1] = src[1]; cold[j][2] = src[2]; cold[j][3] = src[3];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int mu, nu;
+                    int64_t e;
+                    if (!out_index(m, n, j, mu, nu, e)) continue;
                     const double v[4] = {tot[m][n][4 * j], tot[m][n][4 * j + 1], tot[m][n][4 * j + 2],
                                          tot[m][n][4 * j + 3]};
                     double o[4];
@@ -404,11 +446,9 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                         qmul(t, p.alpha_r, o);
                     }
                     if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
-                    double *dst = c64 + 4 * e;
                     if (!beta_zero) {
-                        const double cq[4] = {dst[0], dst[1], dst[2], dst[3]};
                         double u[4];
-                        qmul(p.beta, cq, u);
+                        qmul(p.beta, cold[j], u);
                         if (p.has_right) {
                             const double t[4] = {u[0], u[1], u[2], u[3]};
                             qmul(t, p.beta_r, u);
@@ -416,37 +456,61 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
                         o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                     }
                     if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.0;
+                    double *dst = c64 + 4 * e;
                     dst[0] = o[0]; dst[1] = o[1]; dst[2] = o[2]; dst[3] = o[3];
-                } else {
-                    const float al[4] = {(float)p.alpha[0], (float)p.alpha[1], (float)p.alpha[2], (float)p.alpha[3]};
+                }
+            }
+    } else {
+        const float al[4] = {(float)p.alpha[0], (float)p.alpha[1], (float)p.alpha[2], (float)p.alpha[3]};
+        const float be[4] = {(float)p.beta[0], (float)p.beta[1], (float)p.beta[2], (float)p.beta[3]};
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            f32x4 cold[NB][4];
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int mu, nu;
+                    int64_t e = 0;
+                    cold[n][j] = (f32x4){};
+                    if (!beta_zero && out_index(m, n, j, mu, nu, e))
+                        cold[n][j] = *reinterpret_cast<const f32x4 *>(p.C + 4 * e);
+                }
+#pragma unroll
+            for (int n = 0; n < NB; ++n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int mu, nu;
+                    int64_t e;
+                    if (!out_index(m, n, j, mu, nu, e)) continue;
                     const float v[4] = {tot[m][n][4 * j], tot[m][n][4 * j + 1], tot[m][n][4 * j + 2],
                                         tot[m][n][4 * j + 3]};
                     float o[4];
                     qmul(al, v, o);
                     if (p.has_right) {
-                        const float ar[4] = {(float)p.alpha_r[0], (float)p.alpha_r[1], (float)p.alpha_r[2], (float)p.alpha_r[3]};
+                        const float ar[4] = {(float)p.alpha_r[0], (float)p.alpha_r[1], (float)p.alpha_r[2],
+                                             (float)p.alpha_r[3]};
                         const float t[4] = {o[0], o[1], o[2], o[3]};
                         qmul(t, ar, o);
                     }
                     if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
-                    f32x4 *dst = reinterpret_cast<f32x4 *>(p.C + 4 * e);
                     if (!beta_zero) {
-                        const float be[4] = {(float)p.beta[0], (float)p.beta[1], (float)p.beta[2], (float)p.beta[3]};
-                        const f32x4 c = *dst;
-                        const float cq[4] = {c.x, c.y, c.z, c.w};
+                        const float cq[4] = {cold[n][j].x, cold[n][j].y, cold[n][j].z, cold[n][j].w};
                         float u[4];
                         qmul(be, cq, u);
                         if (p.has_right) {
-                            const float br[4] = {(float)p.beta_r[0], (float)p.beta_r[1], (float)p.beta_r[2], (float)p.beta_r[3]};
+                            const float br[4] = {(float)p.beta_r[0], (float)p.beta_r[1], (float)p.beta_r[2],
+                                                 (float)p.beta_r[3]};
                             const float t[4] = {u[0], u[1], u[2], u[3]};
                             qmul(t, br, u);
                         }
                         o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
                     }
                     if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.f;
-                    *dst = (f32x4){o[0], o[1], o[2], o[3]};
+                    *reinterpret_cast<f32x4 *>(p.C + 4 * e) = (f32x4){o[0], o[1], o[2], o[3]};
                 }
-            }
+        }
+    }
 }
 
 // In-tile byte offsets of the largest tile must stay below 2^31 (the masked

@@ -36,7 +36,9 @@
 //            transposed-operand writes over the banks); fragment reads of one
 //            kappa touch 4 consecutive quaternions = 128 contiguous bytes.
 //   B stage: [kappa][component][nu], plane pitch BN + 1; a fragment read is
-//            16 consecutive doubles per component.  op(B) conjugation and the
+//            16 consecutive doubles per component.  Staging threads store 4 kappa x 4 nu
+//            blocks (op N) or 16 consecutive nu (op T / C), so the component
+//            writes of 16 lanes hit 32 distinct banks.  op(B) conjugation and the
 //            optional left scale s are applied while writing this stage.
 // Triangular operand (TRI = 1: op(A), TRI = 2: op(B); triangular multiply):
 //   a tile walks only the K-tiles the triangle reaches from its rows
@@ -142,10 +144,17 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
         if (!TA) { mu = (q >> 1) % BM; ka = (q >> 1) / BM; }
         else     { ka = (q >> 1) % BK; mu = (q >> 1) / BK; }
     };
+    // B: each group of 16 lanes stores a 4 x 4 (kappa x nu) block when B is read along kappa, so that
+    // its writes into the component planes fall on distinct banks (16 consecutive nu when read along nu).
     auto b_slot = [&](int i, int &nu, int &ka) {
         const int q = tid + NT * i;
-        if (!TB) { ka = q % BK; nu = q / BK; }
-        else     { nu = q % BN; ka = q / BN; }
+        if (!TB) {
+            const int lo = q & 15, hi = q >> 4;
+            ka = (lo >> 2) + 4 * (hi % (BK / 4));
+            nu = (lo & 3) + 4 * (hi / (BK / 4));
+        } else {
+            nu = q % BN; ka = q / BN;
+        }
     };
 
     // fetch K-tile kt into registers; elements at or past K (and whole tiles past
@@ -279,41 +288,55 @@ __global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, in
         __syncthreads();
     }
 
-    // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions
+    // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions.  The old C values of
+    // one MFMA row block are all requested before the first of them is written, so their latencies overlap
+    // (a read after a write to the same array is not reordered by the compiler).
     const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         const int mu = m0 + wave * WM + 4 * m + (lane >> 4);
+        bool ok[4];
+        int64_t e[4];
+        d2 cold[4][2];
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             const int nu = n0 + 16 * n + (lane & 15);
             const bool in_tri = p.uplo == 0 || (p.uplo == 1 ? mu >= nu : mu <= nu);
-            if (mu < p.M && nu < p.N && in_tri) {
-                const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
-                double o[4];
-                qmul(p.alpha, v, o);
-                if (p.has_right) {
-                    const double t[4] = {o[0], o[1], o[2], o[3]};
-                    qmul(t, p.alpha_r, o);
-                }
-                if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
-                const int64_t e = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
-                d2 *dst = reinterpret_cast<d2 *>(p.C + 4 * e);
-                if (!beta_zero) {
-                    const d2 c0 = dst[0], c1 = dst[1];
-                    const double cq[4] = {c0.x, c0.y, c1.x, c1.y};
-                    double u[4];
-                    qmul(p.beta, cq, u);
-                    if (p.has_right) {
-                        const double t[4] = {u[0], u[1], u[2], u[3]};
-                        qmul(t, p.beta_r, u);
-                    }
-                    o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
-                }
-                if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.0;
-                dst[0] = (d2){o[0], o[1]};
-                dst[1] = (d2){o[2], o[3]};
+            ok[n] = mu < p.M && nu < p.N && in_tri;
+            e[n] = p.store_t ? ((int64_t)mu * p.ldc + nu) : ((int64_t)nu * p.ldc + mu);
+            cold[n][0] = cold[n][1] = (d2){0.0, 0.0};
+            if (ok[n] && !beta_zero) {
+                const d2 *src = reinterpret_cast<const d2 *>(p.C + 4 * e[n]);
+                cold[n][0] = src[0];
+                cold[n][1] = src[1];
             }
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            if (!ok[n]) continue;
+            const int nu = n0 + 16 * n + (lane & 15);
+            const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
+            double o[4];
+            qmul(p.alpha, v, o);
+            if (p.has_right) {
+                const double t[4] = {o[0], o[1], o[2], o[3]};
+                qmul(t, p.alpha_r, o);
+            }
+            if (p.store_conj) { o[1] = -o[1]; o[2] = -o[2]; o[3] = -o[3]; }
+            if (!beta_zero) {
+                const double cq[4] = {cold[n][0].x, cold[n][0].y, cold[n][1].x, cold[n][1].y};
+                double u[4];
+                qmul(p.beta, cq, u);
+                if (p.has_right) {
+                    const double t[4] = {u[0], u[1], u[2], u[3]};
+                    qmul(t, p.beta_r, u);
+                }
+                o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
+            }
+            if (p.herm_diag && mu == nu) o[1] = o[2] = o[3] = 0.0;
+            d2 *dst = reinterpret_cast<d2 *>(p.C + 4 * e[n]);
+            dst[0] = (d2){o[0], o[1]};
+            dst[1] = (d2){o[2], o[3]};
         }
     }
 }

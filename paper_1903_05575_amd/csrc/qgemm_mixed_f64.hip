@@ -253,38 +253,51 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
         __syncthreads();
     }
 
-    // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions
+    // ---- epilogue: C <- alpha acc + beta C (left scalars), lane-local quaternions.  The old C values of
+    // four outputs at a time are all requested before the first of them is written, so their latencies
+    // overlap (a read after a write to the same array is not reordered by the compiler).
     const bool beta_zero = p.beta[0] == 0.0 && p.beta[1] == 0.0 && p.beta[2] == 0.0 && p.beta[3] == 0.0;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
         const int pp = p0 + wave * 8 + 4 * m + (lane >> 4);
 #pragma unroll
-        for (int n = 0; n < 8; ++n) {
-            const int qq = q0 + 16 * n + (lane & 15);
-            if (pp >= p.P || qq >= p.Q) continue;
-            const int mu = RIGHT ? qq : pp, nu = RIGHT ? pp : qq;
-            const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
-            double o[4];
-            qmul(p.alpha, v, o);
-            T *dst = Cp + 4 * ((int64_t)nu * p.ldc + mu);
-            if (!beta_zero) {
-                double cq[4];
+        for (int nh = 0; nh < 8; nh += 4) {
+            double cold[4][4];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const int qq = q0 + 16 * (nh + n) + (lane & 15);
+                cold[n][0] = cold[n][1] = cold[n][2] = cold[n][3] = 0.0;
+                if (pp >= p.P || qq >= p.Q || beta_zero) continue;
+                const int mu = RIGHT ? qq : pp, nu = RIGHT ? pp : qq;
+                const T *src = Cp + 4 * ((int64_t)nu * p.ldc + mu);
                 if constexpr (sizeof(T) == 8) {
-                    const d2 c0 = reinterpret_cast<const d2 *>(dst)[0], c1 = reinterpret_cast<const d2 *>(dst)[1];
-                    cq[0] = c0.x; cq[1] = c0.y; cq[2] = c1.x; cq[3] = c1.y;
+                    const d2 c0 = reinterpret_cast<const d2 *>(src)[0], c1 = reinterpret_cast<const d2 *>(src)[1];
+                    cold[n][0] = c0.x; cold[n][1] = c0.y; cold[n][2] = c1.x; cold[n][3] = c1.y;
                 } else {
-                    const f4 c = *reinterpret_cast<const f4 *>(dst);
-                    cq[0] = c.x; cq[1] = c.y; cq[2] = c.z; cq[3] = c.w;
+                    const f4 c = *reinterpret_cast<const f4 *>(src);
+                    cold[n][0] = c.x; cold[n][1] = c.y; cold[n][2] = c.z; cold[n][3] = c.w;
                 }
-                double u[4];
-                qmul(p.beta, cq, u);
-                o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
             }
-            if constexpr (sizeof(T) == 8) {
-                reinterpret_cast<d2 *>(dst)[0] = (d2){o[0], o[1]};
-                reinterpret_cast<d2 *>(dst)[1] = (d2){o[2], o[3]};
-            } else {
-                *reinterpret_cast<f4 *>(dst) = (f4){(float)o[0], (float)o[1], (float)o[2], (float)o[3]};
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const int qq = q0 + 16 * (nh + n) + (lane & 15);
+                if (pp >= p.P || qq >= p.Q) continue;
+                const int mu = RIGHT ? qq : pp, nu = RIGHT ? pp : qq;
+                const double v[4] = {acc[m][nh + n][0], acc[m][nh + n][1], acc[m][nh + n][2], acc[m][nh + n][3]};
+                double o[4];
+                qmul(p.alpha, v, o);
+                if (!beta_zero) {
+                    double u[4];
+                    qmul(p.beta, cold[n], u);
+                    o[0] += u[0]; o[1] += u[1]; o[2] += u[2]; o[3] += u[3];
+                }
+                T *dst = Cp + 4 * ((int64_t)nu * p.ldc + mu);
+                if constexpr (sizeof(T) == 8) {
+                    reinterpret_cast<d2 *>(dst)[0] = (d2){o[0], o[1]};
+                    reinterpret_cast<d2 *>(dst)[1] = (d2){o[2], o[3]};
+                } else {
+                    *reinterpret_cast<f4 *>(dst) = (f4){(float)o[0], (float)o[1], (float)o[2], (float)o[3]};
+                }
             }
         }
     }
