@@ -123,6 +123,29 @@ def cpu_baseline(p, ncols):
                       f"({q.flops(M, ncols, K):.3g} flops in {dt:.1f} s)"}
 
 
+def oracle_single_thread():
+    """The oracle on one thread: the whole 64^3 op N/N problem, and 1024^3 op
+    N/N on its first 32 columns of C (a few seconds)."""
+    import oracle
+    threads = oracle.max_threads()
+    oracle.set_threads(1)
+    out = {}
+    try:
+        for n, ncols in ((64, 64), (1024, 32)):
+            p = W.gemm_problem(W.BASE_SEED + 7, n, n, n, "N", "N", dist="normal")
+            reps = 20 if n == 64 else 1
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                oracle.qgemm("N", "N", n, ncols, n, p["alpha"], p["A"], p["lda"], p["B"][:ncols], p["ldb"],
+                             p["beta"], p["C"][:ncols], p["ldc"])
+            dt = (time.perf_counter() - t0) / reps
+            out[f"{n}_cubed"] = {"gflops": round(q.flops(n, ncols, n) / dt / 1e9, 3),
+                                 "columns": ncols, "seconds": round(dt, 4)}
+    finally:
+        oracle.set_threads(threads)
+    return out
+
+
 def relfro(got, want):
     den = np.linalg.norm(want)
     return float(np.linalg.norm(np.asarray(got, np.float64) - want) / (den if den > 0 else 1.0))
@@ -151,6 +174,7 @@ def variant_split(steps, warmup):
         key = "split_bf16_4096_NC" + ("_rowscaled" if scaled else "")
         tf = fl / (ev * 1e-3) / 1e12
         out[key] = {"ms": round(ev, 3), "tflops_effective": round(tf, 2),
+                    "frac_bf16_peak": round(tf / PEAK_BF16, 4),
                     "bf16_mfma_utilization": round(6 * tf / PEAK_BF16, 4), "split_terms": 6,
                     "rel_err_vs_oracle_sampled": float(f"{relfro(got, want):.3e}")}
         if not scaled:
@@ -651,6 +675,7 @@ def main():
         ncols -= ncols % probe_cols if ncols > probe_cols else 0
         log(f"[bench] CPU oracle baseline on {ncols} columns")
         line["cpu_baseline"] = cpu_baseline(p, ncols)
+        line["cpu_baseline"]["single_thread"] = oracle_single_thread()
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
