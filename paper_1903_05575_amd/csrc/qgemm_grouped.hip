@@ -8,7 +8,7 @@
 // blocks longest-processing-time first, each block receiving a contiguous
 // run of the item array.  Problem descriptors, items and per-block offsets
 // go to device memory once.
-// Run (capture-safe): a single launch of two blocks per CU; block b walks
+// Run (capture-safe): a single launch of three blocks per CU; block b walks
 // items [start[b], start[b+1]).  No allocation, copy, memset or atomic.
 #include "qgemm_bf16x3_tile.hpp"
 
