@@ -646,7 +646,7 @@ def main():
                    "pct_of_fp64_matrix_peak": round(100 * value / PEAK_FP64, 2)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
-                     "traffic": traffic, "kernel": "qgemm_f64_kernel<false,false,false,0>",
+                     "traffic": traffic, "kernel": "qgemm_f64_kernel<32,false,false,false,0>",
                      "kernel_ms": round(ev_ms, 3)},
     }
     del A, B, C

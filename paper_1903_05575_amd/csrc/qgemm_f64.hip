@@ -19,11 +19,14 @@
 // lane-local.  One MFMA = 4 quaternion rows x 16 quaternion columns x one
 // kappa = 64 quaternion multiply-adds.
 //
-// Tiling (block = 256 threads = 4 waves, BM x BN = 64 x 64 quaternions):
-//   wave w owns quaternion rows [16w, 16w+16) x all 64 columns = 4 x 4 MFMA
-//   blocks, 16 accumulators of 4 doubles.  Per kappa a wave reads 4 A and 4 B
-//   fragments (one 8-byte LDS read per lane each) and issues 16 MFMAs.
-//   Two blocks per CU (224 VGPRs), 16.6 + 16.6 KB of LDS per stage.
+// Tiling (block = 256 threads = 4 waves, BM x BN = 32 x 64 or 64 x 64
+// quaternions):
+//   wave w owns quaternion rows [w BM/4, (w+1) BM/4) x all 64 columns = MB x 4
+//   MFMA blocks (MB = 2 or 4) of 4 doubles each.  Per kappa a wave reads MB A
+//   and 4 B fragments (one 8-byte LDS read per lane each) and issues 4 MB
+//   MFMAs.  32-row tiles: three blocks per CU (141 VGPRs, 8.4 + 16.6 KB of
+//   LDS per stage); 64-row tiles: two blocks per CU (224 VGPRs, 16.6 + 16.6
+//   KB per stage).
 //   K is walked in tiles of BK = 8 quaternions through two LDS stages: the
 //   next tile is fetched from HBM into registers at the start of a tile and
 //   written to the other stage in the middle of the current tile's MFMA
@@ -61,9 +64,9 @@ constexpr int B_STAGE = BK * 4 * B_PL;
 constexpr int B_QUATS = BN * BK / NT;            // quaternions of B per thread per tile
 static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
 
-// Tile height: 64 quaternion rows, or 32 for grids whose 64-row tiles cannot
-// fill two blocks per CU (a 1024 x 1024 output has 256 tiles of 64 x 64 for
-// 512 block slots).  Each wave owns BM / 4 rows = MB MFMA row blocks.
+// Tile height: 32 quaternion rows for full outputs (three blocks per CU), 64
+// for triangular outputs and operands (two blocks per CU).  Each wave owns
+// BM / 4 rows = MB MFMA row blocks.
 template <int BMT>
 struct FTile {
     static constexpr int BM = BMT;
@@ -86,7 +89,8 @@ __device__ __forceinline__ double flip(double v, unsigned long long sign)
 constexpr unsigned kOob = 0x80000000u;   // buffer offset read as zero (masked element)
 
 template <int BMT, bool TA, bool TB, bool BS, int TRI>
-__global__ __launch_bounds__(NT, 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n, int nk)
+__global__ __launch_bounds__(NT, BMT == 32 ? 3 : 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n,
+                                                                   int nk)
 {
     using FT = FTile<BMT>;
     constexpr int BM = FT::BM, WM = FT::WM, MB = FT::MB, A_LD = FT::A_LD, A_STAGE = FT::A_STAGE,
@@ -370,31 +374,23 @@ hipError_t launch_ops_t(const GemmDesc<double> &d, hipStream_t stream)
     return d.opB_t ? launch_t<BMT, false, true, BS, TRI>(d, stream) : launch_t<BMT, false, false, BS, TRI>(d, stream);
 }
 
-// Fraction of the block slots (two per CU) that a grid of `tiles` equal tiles
-// keeps busy over its rounds.
-double slot_fill(int64_t tiles, int64_t slots)
-{
-    const int64_t rounds = (tiles + slots - 1) / slots;
-    return rounds > 0 ? (double)tiles / (double)(rounds * slots) : 1.0;
-}
-
-// 64-row tiles, or 32-row tiles for a full (not triangular) output whose
-// 64-row grid fills the block slots clearly worse (a 1024 x 1024 output has
-// 256 tiles of 64 x 64 for 512 slots; 1536 x 1536 has 576, one full round and
-// one of 64).  Measured: 1024^3 from 79% to 84% of the FP64 peak.
+// Full outputs use 32-row tiles: three blocks per CU (141 VGPRs, 50 KB of
+// LDS each, so 12 waves) keep the matrix pipes busier than two blocks of
+// 64-row tiles (224 VGPRs, 8 waves), and twice as many tiles fill small
+// grids better.  Measured on op N/N: 1024^3 from 79% to 84% of the FP64 peak,
+// 2048^3 88.3% -> 88.9%, 4096^3 89.5% -> 90.3%, 8192^3 89.9% -> 90.6%.
+// Triangular outputs (herk) need square tiles and triangular operands (trmm)
+// keep the 64-row tiles their K-range ordering was built for.
 template <bool BS, int TRI>
 hipError_t launch_ops(const GemmDesc<double> &d, hipStream_t stream)
 {
-    if constexpr (TRI == 0) {
-        if (d.uplo == 0) {
-            const int64_t slots = 2 * (int64_t)device_cus();
-            const int64_t tn = (d.N + BN - 1) / BN;
-            const int64_t tiles64 = (int64_t)((d.M + 63) / 64) * tn, tiles32 = (int64_t)((d.M + 31) / 32) * tn;
-            if (slots > 0 && slot_fill(tiles32, slots) > 1.1 * slot_fill(tiles64, slots))
-                return launch_ops_t<32, BS, TRI>(d, stream);
-        }
+    if constexpr (TRI != 0) {
+        return launch_ops_t<64, BS, TRI>(d, stream);
+    } else {
+        if (d.uplo == 0) return launch_ops_t<32, BS, 0>(d, stream);
+        if constexpr (BS) return hipErrorInvalidValue;   // no scaled operand with a triangular output
+        else return launch_ops_t<64, false, 0>(d, stream);
     }
-    return launch_ops_t<64, BS, TRI>(d, stream);
 }
 
 }  // namespace

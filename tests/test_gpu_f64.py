@@ -159,10 +159,10 @@ def test_largest_supported_leading_dimension(gpu, opA, opB):
 
 @pytest.mark.parametrize("opA", "NTCR")
 @pytest.mark.parametrize("opB", "NTCR")
-def test_ops_ragged_both_tile_heights(gpu, opA, opB):
-    """Grids whose 64-row tiles fill the block slots poorly run 32-row tiles,
-    others 64-row tiles: every op pair, ragged in M, N and K, through both
-    (300 x 250: 20 tiles of 64 x 64 -> 32-row; 2040 x 2000: 1024 -> 64-row)."""
+def test_ops_ragged_full_output_tiles(gpu, opA, opB):
+    """Full outputs run 32-row tiles: every op pair, ragged in M, N and K
+    (300 x 250 x 37: partial tiles in every dimension; 2040 x 2000 x 29: a
+    grid of 64 x 32 tiles whose last tile row holds 24 rows)."""
     for i, (M, N, K) in enumerate(((300, 250, 37), (2040, 2000, 29))):
         p = W.gemm_problem(1600 + 32 * i + "NTCR".index(opA) * 4 + "NTCR".index(opB), M, N, K, opA, opB, pad=1)
         Cd = dev(p["C"])
