@@ -64,9 +64,9 @@ constexpr int B_STAGE = BK * 4 * B_PL;
 constexpr int B_QUATS = BN * BK / NT;            // quaternions of B per thread per tile
 static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
 
-// Tile height: 32 quaternion rows for full outputs (three blocks per CU), 64
-// for triangular outputs and operands (two blocks per CU).  Each wave owns
-// BM / 4 rows = MB MFMA row blocks.
+// Tile height: 32 quaternion rows (three blocks per CU), or 64 for triangular
+// outputs (two blocks per CU).  Each wave owns BM / 4 rows = MB MFMA row
+// blocks.
 template <int BMT>
 struct FTile {
     static constexpr int BM = BMT;
@@ -374,18 +374,20 @@ hipError_t launch_ops_t(const GemmDesc<double> &d, hipStream_t stream)
     return d.opB_t ? launch_t<BMT, false, true, BS, TRI>(d, stream) : launch_t<BMT, false, false, BS, TRI>(d, stream);
 }
 
-// Full outputs use 32-row tiles: three blocks per CU (141 VGPRs, 50 KB of
-// LDS each, so 12 waves) keep the matrix pipes busier than two blocks of
-// 64-row tiles (224 VGPRs, 8 waves), and twice as many tiles fill small
-// grids better.  Measured on op N/N: 1024^3 from 79% to 84% of the FP64 peak,
-// 2048^3 88.3% -> 88.9%, 4096^3 89.5% -> 90.3%, 8192^3 89.9% -> 90.6%.
-// Triangular outputs (herk) need square tiles and triangular operands (trmm)
-// keep the 64-row tiles their K-range ordering was built for.
+// Full outputs and triangular operands use 32-row tiles: three blocks per CU
+// (141 VGPRs, 50 KB of LDS each, so 12 waves) keep the matrix pipes busier
+// than two blocks of 64-row tiles (224 VGPRs, 8 waves), and twice as many
+// tiles fill small grids better.  Measured on op N/N: 1024^3 from 79% to 84%
+// of the FP64 peak, 2048^3 88.3% -> 88.9%, 4096^3 89.5% -> 90.3%, 8192^3
+// 89.9% -> 90.6%; an 8192 left lower triangular multiply 131.7 -> 128.5 ms.
+// Triangular outputs (herk) keep square 64 x 64 tiles: a grid of the 32 x 64
+// tiles that meet the triangle measured 129 -> 138 ms at N = K = 8192 (more
+// of each tile on the diagonal is computed and then masked).
 template <bool BS, int TRI>
 hipError_t launch_ops(const GemmDesc<double> &d, hipStream_t stream)
 {
     if constexpr (TRI != 0) {
-        return launch_ops_t<64, BS, TRI>(d, stream);
+        return launch_ops_t<32, BS, TRI>(d, stream);
     } else {
         if (d.uplo == 0) return launch_ops_t<32, BS, 0>(d, stream);
         if constexpr (BS) return hipErrorInvalidValue;   // no scaled operand with a triangular output
