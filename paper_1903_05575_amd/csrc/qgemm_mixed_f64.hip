@@ -27,9 +27,9 @@
 // the result holds all four components of out(p0 + l / 16, q0 + l % 16), so
 // the alpha / beta epilogue is lane-local.
 //
-// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 128
-// quaternions of out.  Wave w owns rows [8w, 8w + 8) x all 128 columns = 2 x
-// 8 MFMA blocks.  A K-tile is 4 MFMA k-steps (16 kappa for a real, 8 for a
+// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 128 (real
+// operand) or 32 x 64 (complex operand) quaternions of out.  Wave w owns rows
+// [8w, 8w + 8) x all BQ columns = 2 x BQ/16 MFMA blocks.  A K-tile is 4 MFMA k-steps (16 kappa for a real, 8 for a
 // complex operand), staged through two LDS stages; the next K-tile is loaded
 // at the start of a tile and written to the other stage after the third
 // k-step.  Masked elements use the out-of-range buffer offset that reads as
@@ -49,16 +49,25 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BP = 32, BQ = 128, NT = 256, STEPS = 4;
+constexpr int BP = 32, NT = 256, STEPS = 4;
+constexpr int BQ_MAX = 128;         // widest tile (bounds the in-tile offsets)
 constexpr int XP = 4 * BP + 4;      // doubles per kappa row of the X stage
-constexpr int YP = BQ + 1;          // doubles per row of the Y stage
 constexpr unsigned kOob = 0x80000000u;
 
 // Storage type T (double or float): operands are read in T and widened
 // exactly to double while staged, so the LDS tiles, the MFMAs and the
 // epilogue arithmetic are FP64 for both; C is stored in T.
+// Tile width: 128 columns (2 x 8 MFMA blocks per wave, two blocks per CU)
+// for a real operand, 64 (2 x 4 blocks, 127 VGPRs, three or more blocks per
+// CU) for a complex one.  Measured at 8192^3: complex x quaternion 127.6 ->
+// 123.9 ms with 64 columns; quaternion x real 66.3 -> 67.6 ms, so it stays at
+// 128.
 template <int KC, typename T>
 struct Shape {
+    static constexpr int BQ = KC == 2 ? 64 : 128;              // quaternion columns of out per tile
+    static constexpr int NQ = BQ / 16;                         // MFMA column blocks per wave
+    static constexpr int YP = BQ + 1;                          // doubles per row of the Y stage
+    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 2;         // resident blocks per CU
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
@@ -70,6 +79,7 @@ struct Shape {
     static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
     static_assert(X_CH * NT == BP * BK * XPER, "X tile must split evenly");
     static_assert(Y_EL * NT == BK * BQ, "Y tile must split evenly");
+    static_assert(BQ <= BQ_MAX && NQ % 4 == 0, "tile width");
 };
 
 // raw register type of one Y element of `bytes` bytes
@@ -88,10 +98,11 @@ __device__ __forceinline__ double flip(double v, bool neg)
 }
 
 template <typename T, int KC, bool RIGHT, bool XT, bool YT>
-__global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int tiles_p, int tiles_q, int nk)
+__global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f64_kernel(MixedDesc p, int tiles_p, int tiles_q,
+                                                                                         int nk)
 {
     using S = Shape<KC, T>;
-    constexpr int BK = S::BK;
+    constexpr int BK = S::BK, BQ = S::BQ, NQ = S::NQ, YP = S::YP;
     constexpr int XPER = S::XPER;
     typedef typename RawY<S::YBYTES>::type YRaw;
     const T *X = static_cast<const T *>(p.X);
@@ -119,11 +130,11 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
     const int x_off = (fk / KC) * XP + (wave * 8 + fp) * 4 + fcomp;   // + step * (4 / KC) * XP + 16 m
     const int y_off = fk * YP + fi;                                     // + step * 4 * YP + 16 n
 
-    d4 acc[2][8];
+    d4 acc[2][NQ];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 8; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < NQ; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
 
     u32x4 rx[S::X_CH];
     YRaw ry[S::Y_EL];
@@ -210,14 +221,14 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
 
     // Multiply the K-tile in stage `Xs`; the registers of the next K-tile are
     // written to `Nxt` after the third k-step.  Fragments of step kk + 1 are
-    // read while step kk's 16 MFMAs run.
+    // read while step kk's MFMAs run.
     auto step_tile = [&](const double *Xs, double *Nxt) {
         const double *Ys = Xs + S::X_STAGE;
-        double a[2][2], b[2][8];
+        double a[2][2], b[2][NQ];
 #pragma unroll
         for (int m = 0; m < 2; ++m) a[0][m] = Xs[x_off + 16 * m];
 #pragma unroll
-        for (int n = 0; n < 8; ++n) b[0][n] = Ys[y_off + 16 * n];
+        for (int n = 0; n < NQ; ++n) b[0][n] = Ys[y_off + 16 * n];
 #pragma unroll
         for (int kk = 0; kk < STEPS; ++kk) {
             const int cur = kk & 1;
@@ -225,14 +236,14 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
 #pragma unroll
                 for (int m = 0; m < 2; ++m) a[cur ^ 1][m] = Xs[(kk + 1) * (4 / KC) * XP + x_off + 16 * m];
 #pragma unroll
-                for (int n = 0; n < 8; ++n) b[cur ^ 1][n] = Ys[(kk + 1) * 4 * YP + y_off + 16 * n];
+                for (int n = 0; n < NQ; ++n) b[cur ^ 1][n] = Ys[(kk + 1) * 4 * YP + y_off + 16 * n];
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 const double am = flip(a[cur][m], neg);
 #pragma unroll
-                for (int n = 0; n < 8; ++n)
+                for (int n = 0; n < NQ; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -261,7 +272,7 @@ __global__ __launch_bounds__(NT, 2) void qgemm_mixed_f64_kernel(MixedDesc p, int
     for (int m = 0; m < 2; ++m) {
         const int pp = p0 + wave * 8 + 4 * m + (lane >> 4);
 #pragma unroll
-        for (int nh = 0; nh < 8; nh += 4) {
+        for (int nh = 0; nh < NQ; nh += 4) {
             double cold[4][4];
 #pragma unroll
             for (int n = 0; n < 4; ++n) {
@@ -312,7 +323,7 @@ hipError_t launch_t(const MixedDesc &d, hipStream_t stream)
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(kern), (int)S::LDS_BYTES, lds_set);
     if (e != hipSuccess) return e;
     const int tiles_p = (d.P + BP - 1) / BP;
-    const int tiles_q = (d.Q + BQ - 1) / BQ;
+    const int tiles_q = (d.Q + S::BQ - 1) / S::BQ;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
     const int nk = alpha_zero ? 0 : (d.K + S::BK - 1) / S::BK;
     const int64_t nblocks = (int64_t)tiles_p * tiles_q;
@@ -344,7 +355,7 @@ bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc, int 
     const int64_t lim = (int64_t)1 << 31;
     const int bk = STEPS * 4 / kc;
     const int64_t fx = 4 * real_bytes * (xt ? ((int64_t)BP * ldx + bk) : ((int64_t)bk * ldx + BP));
-    const int64_t fy = kc * real_bytes * (yt ? ((int64_t)bk * ldy + BQ) : ((int64_t)BQ * ldy + bk));
+    const int64_t fy = kc * real_bytes * (yt ? ((int64_t)bk * ldy + BQ_MAX) : ((int64_t)BQ_MAX * ldy + bk));
     return fx < lim && fy < lim;
 }
 
