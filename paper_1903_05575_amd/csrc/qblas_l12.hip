@@ -157,14 +157,15 @@ __global__ __launch_bounds__(NT) void qdot_final_kernel(int parts, const double 
 // gemv, op N / R: block = GR rows x GC column groups; thread (r, g) sums
 // op(A)[mu][nu] x[nu] over nu = g, g + GC, ... of row mu = mu0 + r (GU
 // columns in flight), then the column groups are summed in order
-// g = 0, 1, ... in LDS.  16 rows of one column are 512 (FP64) or 256 (FP32)
-// contiguous bytes.  Measured at 8192 x 8192: 8 columns in flight is best
-// for FP64, 4 for FP32 (more threads per block or more rows per block were
-// slower for both).
+// g = 0, 1, ... in LDS.  The GR rows of one column are 512 contiguous bytes
+// (FP64, 16 rows) or 128 (FP32, 8 rows).  Measured at 8192 x 8192: 8 columns
+// in flight is best for FP64, 4 for FP32 (8 was 30% slower); 8-row FP32
+// blocks (twice as many blocks in flight) took 0.233 -> 0.197 ms; more
+// threads per block were slower for both.
 template <typename T>
 struct GemvN {
     static constexpr int NTB = NT;
-    static constexpr int GR = 16;
+    static constexpr int GR = sizeof(T) == 8 ? 16 : 8;
     static constexpr int GC = NTB / GR;
     static constexpr int GU = sizeof(T) == 8 ? 8 : 4;
 };
@@ -226,33 +227,37 @@ __global__ __launch_bounds__(GemvN<T>::NTB) void qgemv_n_kernel(int M, int N, in
     }
 }
 
-// gemv, op T / C: wave w of the block computes the TC outputs
-// nu = TC (4 blockIdx + w) + j, j < TC: dot products of columns of A
-// (conjugated for op C) with x, sharing each load of x.  Lanes split the
-// rows and are summed by a fixed butterfly.
+// gemv, op T / C: block b computes the TC outputs nu = TC b + j, j < TC:
+// dot products of columns of A (conjugated for op C) with x, sharing each
+// load of x.  The four waves take interleaved runs of 64 rows (wave w rows
+// 64 w + 256 i + lane), each lane two runs per iteration; lanes are summed by
+// a fixed butterfly and the four waves in order through LDS.
 constexpr int TC = 4;
+constexpr int TW = NT / 64;                     // waves per block
 
 template <typename T, bool CONJ>
 __global__ __launch_bounds__(NT) void qgemv_t_kernel(int M, int N, int nrows, Scalars s, const T *A, int64_t lda,
                                                      const T *x, int64_t incx, bool beta_zero, T *y, int64_t incy)
 {
+    __shared__ double red[TW][TC][4];
     const int lane = threadIdx.x & 63;
-    const int nu0 = TC * (blockIdx.x * (NT / 64) + (threadIdx.x >> 6));
-    if (nu0 >= N) return;                      // whole wave leaves together
+    const int wave = threadIdx.x >> 6;
+    const int nu0 = TC * blockIdx.x;
     int ncol = N - nu0;
     ncol = ncol < TC ? ncol : TC;
     const T *Ac[TC];
 #pragma unroll
     for (int j = 0; j < TC; ++j) Ac[j] = A + 4 * (int64_t)(nu0 + (j < ncol ? j : 0)) * lda;   // spare columns repeat the first
     double acc[TC][4] = {};
-    int mu = lane;
-    for (; mu + 64 < nrows; mu += 2 * 64) {
+    constexpr int RUN = 64 * TW;                 // rows covered by the block per run
+    int mu = 64 * wave + lane;
+    for (; mu + RUN < nrows; mu += 2 * RUN) {
         double a[2][TC][4], xv[2][4];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            load_q(x + 4 * (int64_t)(mu + 64 * u) * incx, xv[u]);
+            load_q(x + 4 * (int64_t)(mu + RUN * u) * incx, xv[u]);
 #pragma unroll
-            for (int j = 0; j < TC; ++j) load_q(Ac[j] + 4 * (int64_t)(mu + 64 * u), a[u][j]);
+            for (int j = 0; j < TC; ++j) load_q(Ac[j] + 4 * (int64_t)(mu + RUN * u), a[u][j]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u)
@@ -282,11 +287,18 @@ __global__ __launch_bounds__(NT) void qgemv_t_kernel(int M, int N, int nrows, Sc
         for (int j = 0; j < TC; ++j)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[j][c] += __shfl_xor(acc[j][c], off);
-    if (lane < ncol) {                          // lane j writes output nu0 + j
-        double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (lane == 0) {
 #pragma unroll
         for (int j = 0; j < TC; ++j)
-            if (j == lane) { v[0] = acc[j][0]; v[1] = acc[j][1]; v[2] = acc[j][2]; v[3] = acc[j][3]; }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[wave][j][c] = acc[j][c];
+    }
+    __syncthreads();
+    if (wave == 0 && lane < ncol) {             // lane j writes output nu0 + j
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < TW; ++w) {
+            v[0] += red[w][lane][0]; v[1] += red[w][lane][1]; v[2] += red[w][lane][2]; v[3] += red[w][lane][3];
+        }
         double o[4];
         qmul(s.alpha, v, o);
         T *yr = y + 4 * (int64_t)(nu0 + lane) * incy;
@@ -367,8 +379,7 @@ hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A
                                lda, x, incx, beta_zero, y, incy);
     } else {
         const int nrows = alpha_zero ? 0 : M;
-        const int per_block = TC * (NT / 64);
-        const dim3 grid((N + per_block - 1) / per_block);
+        const dim3 grid((N + TC - 1) / TC);
         if (conj)
             hipLaunchKernelGGL((qgemv_t_kernel<T, true>), grid, dim3(NT), 0, stream, M, N, nrows, s, A, lda, x, incx,
                                beta_zero, y, incy);
