@@ -24,14 +24,15 @@
 //   wave w owns quaternion rows [w BM/4, (w+1) BM/4) x all 64 columns = MB x 4
 //   MFMA blocks (MB = 2 or 4) of 4 doubles each.  Per kappa a wave reads MB A
 //   and 4 B fragments (one 8-byte LDS read per lane each) and issues 4 MB
-//   MFMAs.  32-row tiles: three blocks per CU (141 VGPRs, 8.4 + 16.6 KB of
-//   LDS per stage); 64-row tiles: two blocks per CU (224 VGPRs, 16.6 + 16.6
-//   KB per stage).
-//   K is walked in tiles of BK = 8 quaternions through two LDS stages: the
-//   next tile is fetched from HBM into registers at the start of a tile and
+//   MFMAs.  32-row tiles of a full output: K-tiles of 4, four blocks per CU
+//   (123 VGPRs, 4.2 + 8.3 KB of LDS per stage); 32-row tiles of a triangular
+//   operand: K-tiles of 8, three blocks per CU (141 VGPRs); 64-row tiles: K-
+//   tiles of 8, two blocks per CU (224 VGPRs, 16.6 + 16.6 KB per stage).
+//   K is walked in tiles of BK quaternions through two LDS stages: the next
+//   tile is fetched from HBM into registers at the start of a tile and
 //   written to the other stage in the middle of the current tile's MFMA
 //   stream (one barrier per tile).  Fragments of the next kappa step are read
-//   from LDS while the current step's 16 MFMAs run.  Operands are read with
+//   from LDS while the current step's MFMAs run.  Operands are read with
 //   buffer loads; masked elements use an out-of-range offset that reads as
 //   zero, so the K-loop has no branches.
 // LDS layouts (doubles):
@@ -57,28 +58,36 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int BN = 64, BK = 8;
+constexpr int BN = 64;
 constexpr int NT = 256;
 constexpr int B_PL = BN + 1;                     // doubles per component plane of the B stage
-constexpr int B_STAGE = BK * 4 * B_PL;
-constexpr int B_QUATS = BN * BK / NT;            // quaternions of B per thread per tile
-static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
 
-// Tile height: 32 quaternion rows (three blocks per CU), or 64 for triangular
-// outputs (two blocks per CU).  Each wave owns BM / 4 rows = MB MFMA row
-// blocks.
-template <int BMT>
+// Tile height: 32 quaternion rows (three or four blocks per CU), or 64 for
+// triangular outputs (two blocks per CU).  Each wave owns BM / 4 rows = MB
+// MFMA row blocks.  K-tile: 8 kappa, or 4 for 32-row tiles of a full output,
+// which halves their LDS (25 KB per block) and registers (123 VGPRs) so that
+// four blocks fit per CU (measured 8192^3 90.5% -> 91.2% of the FP64 peak,
+// 2048^3 88.9% -> 89.8%); triangular operands keep 8 (their masks and K-range
+// bookkeeping spill at four blocks).
+template <int BMT, int TRI = 0>
 struct FTile {
     static constexpr int BM = BMT;
+    static constexpr int BK = (BMT == 32 && TRI == 0) ? 4 : 8;
+    static constexpr int MIN_BLOCKS = BMT == 64 ? 2 : BK == 4 ? 4 : 3;   // resident blocks per CU
+    static constexpr int STORE_AT = BK == 8 ? 5 : 2;   // k-step after which the next K-tile is staged
     static constexpr int WM = BM / 4;            // quaternion rows per wave
     static constexpr int MB = WM / 4;            // MFMA row blocks (4 rows each) per wave
     static constexpr int A_LD = 4 * BM + 4;      // doubles per kappa row of the A stage
     static constexpr int A_STAGE = BK * A_LD;
+    static constexpr int B_STAGE = BK * 4 * B_PL;
     static constexpr int STAGE = A_STAGE + B_STAGE;
     static constexpr int A_CHUNKS = BM * BK * 2 / NT;   // 16-byte chunks of A per thread per tile
+    static constexpr int B_QUATS = BN * BK / NT;        // quaternions of B per thread per tile
     static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
     static_assert(A_CHUNKS * NT == BM * BK * 2, "A tile must split evenly over the block");
+    static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
     static_assert(MB * 16 == BM, "whole MFMA row blocks per wave");
+    static_assert(BK % 4 == 0 && STORE_AT + 1 < BK, "staging point inside the K-tile");
 };
 
 __device__ __forceinline__ double flip(double v, unsigned long long sign)
@@ -89,12 +98,12 @@ __device__ __forceinline__ double flip(double v, unsigned long long sign)
 constexpr unsigned kOob = 0x80000000u;   // buffer offset read as zero (masked element)
 
 template <int BMT, bool TA, bool TB, bool BS, int TRI>
-__global__ __launch_bounds__(NT, BMT == 32 ? 3 : 2) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m, int tiles_n,
-                                                                   int nk)
+__global__ __launch_bounds__(NT, (FTile<BMT, TRI>::MIN_BLOCKS)) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m,
+                                                                                     int tiles_n, int nk)
 {
-    using FT = FTile<BMT>;
-    constexpr int BM = FT::BM, WM = FT::WM, MB = FT::MB, A_LD = FT::A_LD, A_STAGE = FT::A_STAGE,
-                  STAGE = FT::STAGE, A_CHUNKS = FT::A_CHUNKS;
+    using FT = FTile<BMT, TRI>;
+    constexpr int BM = FT::BM, BK = FT::BK, WM = FT::WM, MB = FT::MB, A_LD = FT::A_LD, A_STAGE = FT::A_STAGE,
+                  STAGE = FT::STAGE, A_CHUNKS = FT::A_CHUNKS, B_QUATS = FT::B_QUATS;
     extern __shared__ double smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(NT, BMT == 32 ? 3 : 2) void qgemm_f64_kernel(GemmDe
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            if (kk == BK - 3) store_tile(Nxt);
+            if (kk == FT::STORE_AT) store_tile(Nxt);
         }
     };
 
@@ -348,7 +357,7 @@ __global__ __launch_bounds__(NT, BMT == 32 ? 3 : 2) void qgemm_f64_kernel(GemmDe
 template <int BMT, bool TA, bool TB, bool BS, int TRI>
 hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
 {
-    using FT = FTile<BMT>;
+    using FT = FTile<BMT, TRI>;
     if (d.uplo != 0 && FT::BM != BN) return hipErrorInvalidValue;   // the triangular grid needs square tiles
     static std::atomic<uint64_t> lds_set{0};
     hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(&qgemm_f64_kernel<BMT, TA, TB, BS, TRI>),
@@ -357,7 +366,7 @@ hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
     const int tiles_m = (d.M + FT::BM - 1) / FT::BM;
     const int tiles_n = (d.N + BN - 1) / BN;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
-    const int nk = alpha_zero ? 0 : (d.K + BK - 1) / BK;
+    const int nk = alpha_zero ? 0 : (d.K + FT::BK - 1) / FT::BK;
     const int64_t nblocks = d.uplo == 0 ? (int64_t)tiles_m * tiles_n : (int64_t)tiles_m * (tiles_m + 1) / 2;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
