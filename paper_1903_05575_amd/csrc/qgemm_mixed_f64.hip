@@ -27,12 +27,11 @@
 // the result holds all four components of out(p0 + l / 16, q0 + l % 16), so
 // the alpha / beta epilogue is lane-local.
 //
-// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 128 (real
-// operand) or 32 x 64 (complex operand) quaternions of out.  Wave w owns rows
-// [8w, 8w + 8) x all BQ columns = 2 x BQ/16 MFMA blocks.  A K-tile is 4 MFMA k-steps (16 kappa for a real, 8 for a
-// complex operand), staged through two LDS stages; the next K-tile is loaded
-// at the start of a tile and written to the other stage after the third
-// k-step.  Masked elements use the out-of-range buffer offset that reads as
+// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 64 quaternions
+// of out.  Wave w owns rows [8w, 8w + 8) x all BQ columns = 2 x 4 MFMA blocks.
+// A K-tile is 8 kappa (2 MFMA k-steps for a real, 4 for a complex operand),
+// staged through two LDS stages; the next K-tile is loaded at the start of a
+// tile and written to the other stage after the second-to-last k-step.  Masked elements use the out-of-range buffer offset that reads as
 // zero, so the K-loop has no branches.
 // LDS layouts (doubles):
 //   X stage: [kappa][p][4], row pitch 4 BP + 4
@@ -49,25 +48,29 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BP = 32, NT = 256, STEPS = 4;
-constexpr int BQ_MAX = 128;         // widest tile (bounds the in-tile offsets)
+constexpr int BP = 32, NT = 256;
+constexpr int STEPS_MAX = 4;        // K-tile depth (MFMA k-steps) the in-tile offset check allows for
+constexpr int BQ_MAX = 128;         // tile width the in-tile offset check allows for
 constexpr int XP = 4 * BP + 4;      // doubles per kappa row of the X stage
 constexpr unsigned kOob = 0x80000000u;
 
 // Storage type T (double or float): operands are read in T and widened
 // exactly to double while staged, so the LDS tiles, the MFMAs and the
 // epilogue arithmetic are FP64 for both; C is stored in T.
-// Tile width: 128 columns (2 x 8 MFMA blocks per wave, two blocks per CU)
-// for a real operand, 64 (2 x 4 blocks, 127 VGPRs, three or more blocks per
-// CU) for a complex one.  Measured at 8192^3: complex x quaternion 127.6 ->
-// 123.9 ms with 64 columns; quaternion x real 66.3 -> 67.6 ms, so it stays at
-// 128.
+// Tile: 32 x 64 quaternions of out (2 x 4 MFMA blocks per wave).  K-tile:
+// 4 MFMA k-steps (8 kappa) for a complex operand (127 VGPRs, 2 x 17 KB of LDS,
+// three or more blocks per CU); 2 k-steps (8 kappa) for a real one, whose
+// smaller stages and prefetch (124 VGPRs, 2 x 13 KB) let four blocks share a
+// CU.  Measured at 8192^3 against 32 x 128 tiles with 4 k-steps (two blocks
+// per CU): complex x quaternion 127.6 -> 123.9 ms; quaternion x real 66.3 ->
+// 65.7 ms (67.6 ms with 64 columns and 4 k-steps at three blocks per CU).
 template <int KC, typename T>
 struct Shape {
-    static constexpr int BQ = KC == 2 ? 64 : 128;              // quaternion columns of out per tile
+    static constexpr int BQ = 64;                              // quaternion columns of out per tile
     static constexpr int NQ = BQ / 16;                         // MFMA column blocks per wave
     static constexpr int YP = BQ + 1;                          // doubles per row of the Y stage
-    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 2;         // resident blocks per CU
+    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 4;         // resident blocks per CU
+    static constexpr int STEPS = KC == 2 ? 4 : 2;              // MFMA k-steps per K-tile
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
@@ -79,7 +82,7 @@ struct Shape {
     static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
     static_assert(X_CH * NT == BP * BK * XPER, "X tile must split evenly");
     static_assert(Y_EL * NT == BK * BQ, "Y tile must split evenly");
-    static_assert(BQ <= BQ_MAX && NQ % 4 == 0, "tile width");
+    static_assert(BQ <= BQ_MAX && NQ % 4 == 0 && STEPS <= STEPS_MAX && STEPS >= 2, "tile shape");
 };
 
 // raw register type of one Y element of `bytes` bytes
@@ -230,9 +233,9 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
 #pragma unroll
         for (int n = 0; n < NQ; ++n) b[0][n] = Ys[y_off + 16 * n];
 #pragma unroll
-        for (int kk = 0; kk < STEPS; ++kk) {
+        for (int kk = 0; kk < S::STEPS; ++kk) {
             const int cur = kk & 1;
-            if (kk + 1 < STEPS) {
+            if (kk + 1 < S::STEPS) {
 #pragma unroll
                 for (int m = 0; m < 2; ++m) a[cur ^ 1][m] = Xs[(kk + 1) * (4 / KC) * XP + x_off + 16 * m];
 #pragma unroll
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            if (kk == STEPS - 2) store_tile(Nxt);
+            if (kk == S::STEPS - 2) store_tile(Nxt);
         }
     };
 
@@ -353,7 +356,7 @@ hipError_t launch_kinds(const MixedDesc &d, hipStream_t s)
 bool mixed_ld_supported(int64_t ldx, int64_t ldy, bool xt, bool yt, int kc, int real_bytes)
 {
     const int64_t lim = (int64_t)1 << 31;
-    const int bk = STEPS * 4 / kc;
+    const int bk = STEPS_MAX * 4 / kc;
     const int64_t fx = 4 * real_bytes * (xt ? ((int64_t)BP * ldx + bk) : ((int64_t)bk * ldx + BP));
     const int64_t fy = kc * real_bytes * (yt ? ((int64_t)bk * ldy + BQ_MAX) : ((int64_t)BQ_MAX * ldy + bk));
     return fx < lim && fy < lim;
