@@ -24,10 +24,9 @@
 //   wave w owns quaternion rows [w BM/4, (w+1) BM/4) x all 64 columns = MB x 4
 //   MFMA blocks (MB = 2 or 4) of 4 doubles each.  Per kappa a wave reads MB A
 //   and 4 B fragments (one 8-byte LDS read per lane each) and issues 4 MB
-//   MFMAs.  32-row tiles of a full output: K-tiles of 4, four blocks per CU
-//   (123 VGPRs, 4.2 + 8.3 KB of LDS per stage); 32-row tiles of a triangular
-//   operand: K-tiles of 8, three blocks per CU (141 VGPRs); 64-row tiles: K-
-//   tiles of 8, two blocks per CU (224 VGPRs, 16.6 + 16.6 KB per stage).
+//   MFMAs.  32-row tiles: K-tiles of 4, four blocks per CU (123 VGPRs, 4.2 +
+//   8.3 KB of LDS per stage); 64-row tiles: K-tiles of 8, two blocks per CU
+//   (224 VGPRs, 16.6 + 16.6 KB per stage).
 //   K is walked in tiles of BK quaternions through two LDS stages: the next
 //   tile is fetched from HBM into registers at the start of a tile and
 //   written to the other stage in the middle of the current tile's MFMA
@@ -62,17 +61,17 @@ constexpr int BN = 64;
 constexpr int NT = 256;
 constexpr int B_PL = BN + 1;                     // doubles per component plane of the B stage
 
-// Tile height: 32 quaternion rows (three or four blocks per CU), or 64 for
-// triangular outputs (two blocks per CU).  Each wave owns BM / 4 rows = MB
-// MFMA row blocks.  K-tile: 8 kappa, or 4 for 32-row tiles of a full output,
-// which halves their LDS (25 KB per block) and registers (123 VGPRs) so that
-// four blocks fit per CU (measured 8192^3 90.5% -> 91.2% of the FP64 peak,
-// 2048^3 88.9% -> 89.8%); triangular operands keep 8 (their masks and K-range
-// bookkeeping spill at four blocks).
+// Tile height: 32 quaternion rows (four blocks per CU), or 64 for triangular
+// outputs (two blocks per CU).  Each wave owns BM / 4 rows = MB MFMA row
+// blocks.  K-tile: 4 kappa for 32-row tiles, which halves their LDS (25 KB
+// per block) and prefetch registers (123 VGPRs) so that four blocks fit per
+// CU (measured 8192^3 90.5% -> 91.2% of the FP64 peak, 2048^3 88.9% ->
+// 89.8%; an 8192 triangular multiply 127.9 -> 126.7 ms, although its masks
+// then spill a few registers); 8 kappa for 64-row tiles.
 template <int BMT, int TRI = 0>
 struct FTile {
     static constexpr int BM = BMT;
-    static constexpr int BK = (BMT == 32 && TRI == 0) ? 4 : 8;
+    static constexpr int BK = BMT == 32 ? 4 : 8;
     static constexpr int MIN_BLOCKS = BMT == 64 ? 2 : BK == 4 ? 4 : 3;   // resident blocks per CU
     static constexpr int STORE_AT = BK == 8 ? 5 : 2;   // k-step after which the next K-tile is staged
     static constexpr int WM = BM / 4;            // quaternion rows per wave
