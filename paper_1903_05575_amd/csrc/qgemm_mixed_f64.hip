@@ -27,11 +27,12 @@
 // the result holds all four components of out(p0 + l / 16, q0 + l % 16), so
 // the alpha / beta epilogue is lane-local.
 //
-// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 64 quaternions
-// of out.  Wave w owns rows [8w, 8w + 8) x all BQ columns = 2 x 4 MFMA blocks.
-// A K-tile is 8 kappa (2 MFMA k-steps for a real, 4 for a complex operand),
-// staged through two LDS stages; the next K-tile is loaded at the start of a
-// tile and written to the other stage after the second-to-last k-step.  Masked elements use the out-of-range buffer offset that reads as
+// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 128 (real
+// operand) or 32 x 64 (complex operand) quaternions of out.  Wave w owns rows
+// [8w, 8w + 8) x all BQ columns = 2 x BQ/16 MFMA blocks.  A K-tile is 4 MFMA
+// k-steps (16 kappa for a real, 8 for a complex operand), staged through two
+// LDS stages; the next K-tile is loaded at the start of a tile and written to
+// the other stage after the third k-step.  Masked elements use the out-of-range buffer offset that reads as
 // zero, so the K-loop has no branches.
 // LDS layouts (doubles):
 //   X stage: [kappa][p][4], row pitch 4 BP + 4
@@ -57,20 +58,20 @@ constexpr unsigned kOob = 0x80000000u;
 // Storage type T (double or float): operands are read in T and widened
 // exactly to double while staged, so the LDS tiles, the MFMAs and the
 // epilogue arithmetic are FP64 for both; C is stored in T.
-// Tile: 32 x 64 quaternions of out (2 x 4 MFMA blocks per wave).  K-tile:
-// 4 MFMA k-steps (8 kappa) for a complex operand (127 VGPRs, 2 x 17 KB of LDS,
-// three or more blocks per CU); 2 k-steps (8 kappa) for a real one, whose
-// smaller stages and prefetch (124 VGPRs, 2 x 13 KB) let four blocks share a
-// CU.  Measured at 8192^3 against 32 x 128 tiles with 4 k-steps (two blocks
-// per CU): complex x quaternion 127.6 -> 123.9 ms; quaternion x real 66.3 ->
-// 65.7 ms (67.6 ms with 64 columns and 4 k-steps at three blocks per CU).
+// Tile: 32 x 128 quaternions of out (2 x 8 MFMA blocks per wave, two blocks
+// per CU) for a real operand, 32 x 64 (2 x 4 blocks, 127 VGPRs, three or more
+// blocks per CU) for a complex one; 4 MFMA k-steps per K-tile (16 kappa real,
+// 8 complex).  Measured at 8192^3: complex x quaternion 127.6 -> 123.9 ms with
+// 64 columns.  For a real operand neither 64 columns (67.6 ms against 66.3) nor
+// 64 columns with 2 k-steps at four blocks per CU (between 1% faster and 2%
+// slower depending on the host) was a clear gain, so it keeps 128 columns.
 template <int KC, typename T>
 struct Shape {
-    static constexpr int BQ = 64;                              // quaternion columns of out per tile
+    static constexpr int BQ = KC == 2 ? 64 : 128;              // quaternion columns of out per tile
     static constexpr int NQ = BQ / 16;                         // MFMA column blocks per wave
     static constexpr int YP = BQ + 1;                          // doubles per row of the Y stage
-    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 4;         // resident blocks per CU
-    static constexpr int STEPS = KC == 2 ? 4 : 2;              // MFMA k-steps per K-tile
+    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 2;         // resident blocks per CU
+    static constexpr int STEPS = 4;                            // MFMA k-steps per K-tile
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
