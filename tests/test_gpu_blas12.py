@@ -90,6 +90,25 @@ def test_qgemv(gpu, p, trans):
     assert np.isnan(got[1::3]).all()
 
 
+@pytest.mark.parametrize("p", "ds")
+@pytest.mark.parametrize("trans", "NTC")
+def test_qgemv_edge_shapes(gpu, p, trans):
+    """Shapes at the edges of the block layouts: op T/C splits the rows of a
+    block over four waves in runs of 64 (fewer rows than one run leaves waves
+    with nothing), op N takes 16 (FP64) or 8 (FP32) rows per block; output
+    counts below, at and above the four outputs of an op T/C block."""
+    for i, (M, N) in enumerate(((1, 1), (5, 3), (63, 4), (64, 5), (65, 8), (257, 9), (8, 1), (17, 2))):
+        g = W.rng(1360 + 10 * i + "NTC".index(trans) + 5 * (p == "s"))
+        A = W.qmatrix(g, M, N, ld=M + 1, dtype=NP[p])
+        nx, ny = (M, N) if trans in "TC" else (N, M)
+        x, y = W.qvector(g, nx, dtype=NP[p]), W.qvector(g, ny, dtype=NP[p])
+        al, be = W.quaternion(g), W.quaternion(g)
+        yd = dev(y)
+        q.qgemv(trans, M, N, al, dev(A), M + 1, dev(x), 1, be, yd, 1)
+        want = oracle.qgemv(trans, M, N, al, A, M + 1, x, 1, be, y, 1)
+        assert relfro(host(yd), want) <= TOL[p], (M, N)
+
+
 @pytest.mark.parametrize("trans", "NC")
 def test_qgemv_large_and_rules(gpu, trans):
     g = W.rng(1350 + (trans == "C"))
