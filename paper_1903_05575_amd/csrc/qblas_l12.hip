@@ -171,7 +171,7 @@ struct GemvN {
 };
 
 template <typename T, bool CONJ>
-__global__ __launch_bounds__(GemvN<T>::NTB) void qgemv_n_kernel(int M, int N, int ncols, Scalars s, const T *A,
+__global__ __launch_bounds__(GemvN<T>::NTB) void qgemv_n_kernel(int M, int ncols, Scalars s, const T *A,
                                                                 int64_t lda, const T *x, int64_t incx,
                                                                 bool beta_zero, T *y, int64_t incy)
 {
@@ -236,7 +236,7 @@ constexpr int TC = 4;
 constexpr int TW = NT / 64;                     // waves per block
 
 template <typename T, bool CONJ>
-__global__ __launch_bounds__(NT) void qgemv_t_kernel(int M, int N, int nrows, Scalars s, const T *A, int64_t lda,
+__global__ __launch_bounds__(NT) void qgemv_t_kernel(int N, int nrows, Scalars s, const T *A, int64_t lda,
                                                      const T *x, int64_t incx, bool beta_zero, T *y, int64_t incy)
 {
     __shared__ double red[TW][TC][4];
@@ -372,19 +372,19 @@ hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A
         const int ncols = alpha_zero ? 0 : N;
         const dim3 grid((M + GemvN<T>::GR - 1) / GemvN<T>::GR);
         if (conj)
-            hipLaunchKernelGGL((qgemv_n_kernel<T, true>), grid, dim3(GemvN<T>::NTB), 0, stream, M, N, ncols, s, A,
+            hipLaunchKernelGGL((qgemv_n_kernel<T, true>), grid, dim3(GemvN<T>::NTB), 0, stream, M, ncols, s, A,
                                lda, x, incx, beta_zero, y, incy);
         else
-            hipLaunchKernelGGL((qgemv_n_kernel<T, false>), grid, dim3(GemvN<T>::NTB), 0, stream, M, N, ncols, s, A,
+            hipLaunchKernelGGL((qgemv_n_kernel<T, false>), grid, dim3(GemvN<T>::NTB), 0, stream, M, ncols, s, A,
                                lda, x, incx, beta_zero, y, incy);
     } else {
         const int nrows = alpha_zero ? 0 : M;
         const dim3 grid((N + TC - 1) / TC);
         if (conj)
-            hipLaunchKernelGGL((qgemv_t_kernel<T, true>), grid, dim3(NT), 0, stream, M, N, nrows, s, A, lda, x, incx,
+            hipLaunchKernelGGL((qgemv_t_kernel<T, true>), grid, dim3(NT), 0, stream, N, nrows, s, A, lda, x, incx,
                                beta_zero, y, incy);
         else
-            hipLaunchKernelGGL((qgemv_t_kernel<T, false>), grid, dim3(NT), 0, stream, M, N, nrows, s, A, lda, x,
+            hipLaunchKernelGGL((qgemv_t_kernel<T, false>), grid, dim3(NT), 0, stream, N, nrows, s, A, lda, x,
                                incx, beta_zero, y, incy);
     }
     return hipGetLastError();
