@@ -53,6 +53,19 @@ def test_trmm_f64(gpu, side, uplo, trans, diag):
 
 @pytest.mark.parametrize("side", "LR")
 @pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("diag", "NU")
+def test_trmm_f64_small_triangles(gpu, side, uplo, diag):
+    """Triangles smaller than, equal to and just past one K-tile (4) and one
+    32-row tile, where every K-tile a tile reaches crosses the diagonal."""
+    for i, (n, other) in enumerate(((1, 3), (3, 5), (4, 4), (5, 2), (31, 7), (32, 33), (33, 9))):
+        trans = "NTCR"[i % 4]
+        M, N = (n, other) if side == "L" else (other, n)
+        seed = 1500 + 50 * i + "LR".index(side) * 4 + "LU".index(uplo) * 2 + "NU".index(diag)
+        check(W.trmm_problem(seed, side, uplo, trans, diag, M, N, pad=1), "f64")
+
+
+@pytest.mark.parametrize("side", "LR")
+@pytest.mark.parametrize("uplo", "LU")
 @pytest.mark.parametrize("trans", "NC")
 @pytest.mark.parametrize("diag", "NU")
 def test_trmm_f32(gpu, side, uplo, trans, diag):
