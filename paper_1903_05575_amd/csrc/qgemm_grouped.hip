@@ -9,8 +9,8 @@
 // run of the item array.  The block slots of the assignment are numbered so
 // that consecutive slots run on one XCD: the equal-cost tiles of a problem,
 // dealt one after another, then mostly share one L2 for its A and B panels
-// (2.08 -> 2.01 ms on 4096 problems of sizes log-uniform in [8, 512]).  Problem descriptors, items and per-block offsets
-// go to device memory once.
+// (2.08 -> 2.01 ms on 4096 problems of sizes log-uniform in [8, 512]).
+// Problem descriptors, items and per-block offsets go to device memory once.
 // Run (capture-safe): a single launch of three blocks per CU; block b walks
 // items [start[b], start[b+1]).  No allocation, copy, memset or atomic.
 #include "qgemm_bf16x3_tile.hpp"
