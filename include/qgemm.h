@@ -151,7 +151,9 @@ qgemm_status_t qgemm_s(int opA, int opB, int64_t M, int64_t N, int64_t K,
 /*
  * qgemm_s_c64 -- as qgemm_s, but C is an array of double: the accumulated
  * product is widened and alpha, beta and the update of C are done in FP64
- * (for callers that keep the result in double).  C must be 32-byte aligned.
+ * (for callers that keep the result in double).  C must be 32-byte aligned
+ * (one double quaternion); A and B, arrays of float, 16-byte aligned as in
+ * qgemm_s.
  */
 qgemm_status_t qgemm_s_c64(int opA, int opB, int64_t M, int64_t N, int64_t K,
                            const double *alpha, const float *A, int64_t lda,

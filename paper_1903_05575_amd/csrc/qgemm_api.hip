@@ -53,8 +53,10 @@ static_assert(QGEMM_DOT_WORK_DOUBLES >= 4 * qg::kDotParts, "dot workspace holds 
 // Validate a GEMM call.  Argument numbering follows the public signatures:
 // 1 opA, 2 opB, 3 M, 4 N, 5 K, 6 alpha, 7 A, 8 lda, 9 B, 10 ldb, 11 beta,
 // 12 C, 13 ldc.  `align` is the byte size of one element of C (and the
-// alignment asked of every operand); `ab_bytes` the byte size of one element
-// of A and B, for the check that C overlaps neither (0: the caller checks).
+// alignment asked of C); `ab_bytes` the byte size of one element of A and B
+// (the alignment asked of them, and the element size of the check that C
+// overlaps neither); 0: A and B are aligned to `align` and the caller checks
+// the overlap.
 qgemm_status_t validate(int opA, int opB, int64_t M, int64_t N, int64_t K, const double *alpha,
                         const void *A, int64_t lda, const void *B, int64_t ldb, const double *beta,
                         const void *C, int64_t ldc, uintptr_t align, int64_t ab_bytes)
@@ -86,8 +88,9 @@ qgemm_status_t validate(int opA, int opB, int64_t M, int64_t N, int64_t K, const
     if (reads_ab && !A) return fail(QGEMM_ERR_INVALID_ARG, 7);
     if (reads_ab && !B) return fail(QGEMM_ERR_INVALID_ARG, 9);
     if (!C) return fail(QGEMM_ERR_INVALID_ARG, 12);
-    if (reads_ab && (reinterpret_cast<uintptr_t>(A) % align)) return fail(QGEMM_ERR_MISALIGNED, 7);
-    if (reads_ab && (reinterpret_cast<uintptr_t>(B) % align)) return fail(QGEMM_ERR_MISALIGNED, 9);
+    const uintptr_t ab_align = ab_bytes ? (uintptr_t)ab_bytes : align;
+    if (reads_ab && (reinterpret_cast<uintptr_t>(A) % ab_align)) return fail(QGEMM_ERR_MISALIGNED, 7);
+    if (reads_ab && (reinterpret_cast<uintptr_t>(B) % ab_align)) return fail(QGEMM_ERR_MISALIGNED, 9);
     if (reinterpret_cast<uintptr_t>(C) % align) return fail(QGEMM_ERR_MISALIGNED, 12);
     // C is written by some tiles while others still read A and B
     if (reads_ab && ab_bytes) {
@@ -150,8 +153,11 @@ int adjoint_op(int op)
 }
 
 // Gradient of L = <G, alpha op(A) op(B) + beta C0> (real inner product of the
-// components) with respect to the stored A, B and C0.  With the scalar
-// derivation of the oracle's header:
+// components) with respect to the stored A, B and C0.  For quaternions
+// <x, q y> = <conj(q) x, y> and <x, y q> = <x conj(q), y> (the 4 x 4 matrices
+// of left and right multiplication by q are transposed by conjugating q), so
+// <G, alpha a b> = <conj(alpha) G conj(b), a> = <conj(a) conj(alpha) G, b>
+// term by term, and summing over the products of each output:
 //   d op(A) = conj(alpha) G op(B)^H                (left scalar)
 //   d op(B) = op(A)^H (conj(alpha) G)              (scalar between the factors)
 //   dC0     = conj(beta) G

@@ -256,19 +256,26 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
     // fetch K-tile kt into registers (tiles at or past K read as zeros)
     auto load_tile = [&](int kt) {
         const int k0 = kt * BK;
-        const int krem = p.K - k0;
+        // the prefetch past this tile's K-range reads nothing (for a triangular
+        // operand that K-tile lies in the triangle that must not be read)
+        const int krem = (kt < kt1 ? p.K : 0) - k0;
         const float *Ab = p.A + 4 * (TA ? ((int64_t)m0 * p.lda + k0) : ((int64_t)k0 * p.lda + m0));
         const float *Bb = p.B + 4 * (TB ? ((int64_t)k0 * p.ldb + n0) : ((int64_t)n0 * p.ldb + k0));
         const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, 0x7fffffff, 0x00020000);
         const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, 0x7fffffff, 0x00020000);
+        // only K-tiles that cross the diagonal of a triangular operand need its mask (uniform per block)
+        const bool diagA = TRI == 1 && k0 < m0 + BM && k0 + BK > m0;
+        const bool diagB = TRI == 2 && k0 < n0 + BN && k0 + BK > n0;
         if constexpr (TRI != 0) unit_bits = 0;
 #pragma unroll
         for (int i = 0; i < TL::A_Q; ++i) {
             bool ok = a_k[i] < krem;
             if constexpr (TRI == 1) {
-                const int gm = m0 + a_r[i], gk = k0 + a_k[i];
-                ok = ok && (p.tri_lower ? gk <= gm : gk >= gm) && !(p.tri_unit && gk == gm);
-                if (p.tri_unit && gk == gm && gm < p.M) unit_bits |= 1u << i;
+                if (diagA) {
+                    const int gm = m0 + a_r[i], gk = k0 + a_k[i];
+                    ok = ok && (p.tri_lower ? gk <= gm : gk >= gm) && !(p.tri_unit && gk == gm);
+                    if (p.tri_unit && gk == gm && gm < p.M) unit_bits |= 1u << i;
+                }
             }
             ra[i] = __builtin_amdgcn_raw_buffer_load_b128(rA, ok ? a_off[i] : kOob, 0, 0);
         }
@@ -276,9 +283,11 @@ __device__ __forceinline__ void split_tile(const GemmDesc<float> &p, double *c64
         for (int i = 0; i < TL::B_Q; ++i) {
             bool ok = b_k[i] < krem;
             if constexpr (TRI == 2) {
-                const int gn = n0 + b_c[i], gk = k0 + b_k[i];
-                ok = ok && (p.tri_lower ? gk >= gn : gk <= gn) && !(p.tri_unit && gk == gn);
-                if (p.tri_unit && gk == gn && gn < p.N) unit_bits |= 1u << i;
+                if (diagB) {
+                    const int gn = n0 + b_c[i], gk = k0 + b_k[i];
+                    ok = ok && (p.tri_lower ? gk >= gn : gk <= gn) && !(p.tri_unit && gk == gn);
+                    if (p.tri_unit && gk == gn && gn < p.N) unit_bits |= 1u << i;
+                }
             }
             rb[i] = __builtin_amdgcn_raw_buffer_load_b128(rB, ok ? b_off[i] : kOob, 0, 0);
         }

@@ -382,12 +382,13 @@ hipError_t launch_ops_t(const GemmDesc<double> &d, hipStream_t stream)
     return d.opB_t ? launch_t<BMT, false, true, BS, TRI>(d, stream) : launch_t<BMT, false, false, BS, TRI>(d, stream);
 }
 
-// Full outputs and triangular operands use 32-row tiles: three blocks per CU
-// (141 VGPRs, 50 KB of LDS each, so 12 waves) keep the matrix pipes busier
-// than two blocks of 64-row tiles (224 VGPRs, 8 waves), and twice as many
-// tiles fill small grids better.  Measured on op N/N: 1024^3 from 79% to 84%
-// of the FP64 peak, 2048^3 88.3% -> 88.9%, 4096^3 89.5% -> 90.3%, 8192^3
-// 89.9% -> 90.6%; an 8192 left lower triangular multiply 131.7 -> 128.5 ms.
+// Full outputs and triangular operands use 32 x 64 tiles with 4-kappa K-tiles
+// (FTile<32>): four blocks per CU (123 VGPRs, 25 KB of LDS each, so 16 waves)
+// keep the matrix pipes busier than two blocks of 64-row tiles (224 VGPRs,
+// 8 waves), and twice as many tiles fill small grids better.  Measured on op
+// N/N against the 64-row tiles: 2048^3 88.3% -> 89.8-90.0% of the FP64 peak,
+// 4096^3 89.5% -> 90.8-91.2%, 8192^3 89.9% -> 91.1-91.6%; an 8192 left lower
+// triangular multiply 131.7 -> 126.7 ms.
 // Triangular outputs (herk) keep square 64 x 64 tiles: a grid of the 32 x 64
 // tiles that meet the triangle measured 129 -> 138 ms at N = K = 8192 (more
 // of each tile on the diagonal is computed and then masked).

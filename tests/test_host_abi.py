@@ -75,6 +75,24 @@ def test_validation_s_split_terms(L):
     assert rc == 2 and L.qgemm_last_invalid_arg() == 7
 
 
+def test_validation_s_c64_alignment(L):
+    """qgemm_s_c64 asks 16-byte alignment of its float A and B (as qgemm_s)
+    and 32-byte alignment of its double C: a sub-matrix view of A or B offset
+    by one float quaternion is accepted (the call then stops at the bad
+    split_terms, argument 14); C offset by 16 bytes is refused."""
+    for fn in (L.qgemm_s, L.qgemm_s_c64):
+        rc = fn(0, 0, 4, 4, 4, ONE, FAKE + 16, 4, FAKE_B + 16, 4, ONE, FAKE_C, 4, 5, None)
+        assert rc == 1 and L.qgemm_last_invalid_arg() == 14
+        rc = fn(0, 0, 4, 4, 4, ONE, FAKE + 8, 4, FAKE_B, 4, ONE, FAKE_C, 4, 6, None)
+        assert rc == 2 and L.qgemm_last_invalid_arg() == 7
+        rc = fn(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE_B + 8, 4, ONE, FAKE_C, 4, 6, None)
+        assert rc == 2 and L.qgemm_last_invalid_arg() == 9
+    rc = L.qgemm_s_c64(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE_B, 4, ONE, FAKE_C + 16, 4, 6, None)
+    assert rc == 2 and L.qgemm_last_invalid_arg() == 12
+    rc = L.qgemm_s(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE_B, 4, ONE, FAKE_C + 16, 4, 5, None)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 14
+
+
 def test_validation_backward(L):
     rc = L.qgemm_backward_d(0, 0, 4, 4, 4, ONE, FAKE, 4, FAKE, 4, FAKE, 3, ONE, FAKE, 4, FAKE, 4, FAKE, 4, None)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 12

@@ -364,6 +364,29 @@ def test_scalar_placement_brute_force(opA, opB):
     np.testing.assert_allclose(qref.logical(got, M, N), want, atol=1e-12)
 
 
+@pytest.mark.parametrize("which", ["aL", "aM", "aR"])
+def test_scalar_placement_zero_scalar_skips_product(which):
+    """Any of aL, aM, aR zero makes the product term vanish, so A and B are
+    not read (all NaN here) and the result is bL C bR, brute force over the
+    basis table; bL zero on top of that gives zeros without reading C."""
+    M, N, K = 3, 4, 5
+    p = W.gemm_problem(73, M, N, K, "T", "C", dist="normal", pad=1)
+    g = W.rng(12)
+    sc = {k: g.standard_normal(4) for k in ("aL", "aM", "aR", "bL", "bR")}
+    sc[which] = np.zeros(4)
+    An, Bn = np.full_like(p["A"], np.nan), np.full_like(p["B"], np.nan)
+    got = oracle.qgemm_ex("T", "C", M, N, K, sc["aL"], sc["aM"], sc["aR"], An, p["lda"], Bn, p["ldb"],
+                          sc["bL"], sc["bR"], p["C"], p["ldc"])
+    C = qref.logical(p["C"], M, N)
+    want = np.array([[qref.bf_mul(qref.bf_mul(sc["bL"], C[mu, nu]), sc["bR"]) for nu in range(N)]
+                     for mu in range(M)])
+    np.testing.assert_allclose(qref.logical(got, M, N), want, rtol=0, atol=1e-14)
+    Cn = np.full_like(p["C"], np.nan)
+    got = oracle.qgemm_ex("T", "C", M, N, K, sc["aL"], sc["aM"], sc["aR"], An, p["lda"], Bn, p["ldb"],
+                          np.zeros(4), sc["bR"], Cn, p["ldc"])
+    np.testing.assert_array_equal(qref.logical(got, M, N), np.zeros((M, N, 4)))
+
+
 def test_scalar_placement_complex_embedding():
     """aL A (aM I) B aR + bL C bR through complex128 products on the block
     representation: scalar matrices qI embed as block scalar matrices, and a
@@ -429,6 +452,32 @@ def test_qherk_vs_complex_embedding(uplo, trans):
                 np.testing.assert_allclose(gl[mu, nu], want[mu, nu], atol=1e-12)
     # padding rows of C untouched
     assert np.isnan(got[:, n:]).all()
+
+
+@pytest.mark.parametrize("uplo", "LU")
+def test_qherk_quick_return_and_alpha_zero(uplo):
+    """BLAS quick return: (alpha == 0 or k == 0) with beta == 1 leaves C as it
+    is, bit for bit, diagonal vector part and NaN in A included.  alpha == 0
+    with beta != 1 is no quick return: the triangle becomes beta C (brute
+    force) and the diagonal's vector part is zeroed."""
+    n, k = 6, 4
+    g = W.rng(67)
+    A = np.full((k, n + 1, 4), np.nan)
+    C = W.qmatrix(g, n, n, ld=n + 1)
+    for alpha, kk in ((0.0, k), (0.8, 0)):
+        got = oracle.qherk(uplo, "N", n, kk, alpha, A, n + 1, 1.0, C, n + 1)
+        np.testing.assert_array_equal(got, C)
+    got = qref.logical(oracle.qherk(uplo, "N", n, k, 0.0, A, n + 1, 0.5, C, n + 1), n, n)
+    cl = qref.logical(C, n, n)
+    for mu in range(n):
+        for nu in range(n):
+            inside = mu >= nu if uplo == "L" else mu <= nu
+            if not inside:
+                np.testing.assert_array_equal(got[mu, nu], cl[mu, nu])
+            elif mu == nu:
+                np.testing.assert_array_equal(got[mu, mu], [0.5 * cl[mu, mu, 0], 0.0, 0.0, 0.0])
+            else:
+                np.testing.assert_array_equal(got[mu, nu], 0.5 * cl[mu, nu])
 
 
 def test_qherk_matches_hermitian_product():
@@ -748,6 +797,9 @@ MUTANTS = [
     ("if (conj) conj_q(x + 4 * i * incx, xi);", "if (conj) conj_q(y + 4 * i * incy, xi);"),   # dotc conjugates y
     ("Q[4 * (r + c * sr) + k] = X[type * (r + c * ldx) + k];",
      "Q[4 * (r + c * sr) + (type == 2 ? 2 * k : k)] = X[type * (r + c * ldx) + k];"),  # complex into e0, e2
+    ("if ((alpha == 0.0 || k == 0) && beta == 1.0) return 0;",
+     "if ((alpha == 0.0 || k == 0) && beta == 2.0) return 0;"),   # herk loses its quick return
+    ("    if (az) K = 0;\n", "    if (az) K = K;\n"),           # ex forms the product with a zero scalar
 ]
 
 
@@ -826,6 +878,25 @@ def _mutant_pins_fail(so):
     want = qref.qgemm_via_complex("C", "N", 1, 1, 3, al, np.ascontiguousarray(x[None]),
                                   np.ascontiguousarray(x2[None]), [0.0] * 4, np.zeros((1, 1, 4)))[0, 0]
     if not np.allclose(r, want):
+        return True
+    # herk quick return: alpha == 0 with beta == 1 leaves C (diagonal vector part included) as it is
+    L.oracle_qherk.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, ctypes.c_double, dp, i64, ctypes.c_double,
+                               dp, i64]
+    Ch = W.qmatrix(g, 4, 4)
+    out = np.ascontiguousarray(Ch.copy())
+    L.oracle_qherk(0, 0, 4, 3, 0.0, P(np.full((3, 4, 4), np.nan)), 4, 1.0, P(out), 4)
+    if not np.array_equal(out, Ch):
+        return True
+    # a zero outer or middle scalar: A and B (NaN) are not read, the result is bL C bR
+    L.oracle_qgemm_ex.argtypes = [ctypes.c_int, ctypes.c_int, i64, i64, i64, dp, dp, dp, dp, i64, dp, i64, dp, dp,
+                                  dp, i64]
+    bL, bR = np.array([0.5, -1.0, 0.25, 2.0]), np.array([1.5, 0.5, -0.5, 1.0])
+    out = np.ascontiguousarray(Ch.copy())
+    nan = np.full((3, 4, 4), np.nan)
+    L.oracle_qgemm_ex(0, 0, 4, 4, 3, P(np.zeros(4)), None, None, P(nan), 4, P(nan.copy()), 3, P(bL), P(bR),
+                      P(out), 4)
+    want = np.array([[qref.bf_mul(qref.bf_mul(bL, Ch[j, i]), bR) for i in range(4)] for j in range(4)])
+    if not np.allclose(out, want, atol=1e-14):
         return True
     return False
 
