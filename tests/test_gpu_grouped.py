@@ -1,5 +1,7 @@
 """GPU checks of the grouped (batched) FP32 path: every problem against the
-FP64 oracle, every tile class, graph capture and replay."""
+FP64 oracle (relative Frobenius bar 1e-6 for 6 and 9 products, 3e-5 for 3,
+globally and per 32 x 32 block, and every real within the split path's
+componentwise bound), every tile class, graph capture and replay."""
 import numpy as np
 import pytest
 import torch
@@ -7,7 +9,7 @@ import torch
 import oracle
 import workloads as W
 import paper_1903_05575_amd as q
-from tests.gpu_util import dev, host, relfro
+from tests.gpu_util import SPLIT_BAR, assert_parity, dev, host, logical, relfro, split_error_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -31,15 +33,21 @@ def to_dev(probs):
     return [dict(pr, A=dev(pr["A"]), B=dev(pr["B"]), C=dev(pr["C"])) for pr in probs]
 
 
-def check_all(probs, dprobs, opA, opB, alpha, beta, bound=1e-6):
-    worst = 0.0
-    for pr, dp in zip(probs, dprobs):
-        want = oracle.qgemm(opA, opB, pr["M"], pr["N"], pr["K"], alpha, pr["A"], pr["lda"], pr["B"], pr["ldb"],
+def check_all(probs, dprobs, opA, opB, alpha, beta, terms=6):
+    """Every problem against the oracle; returns the worst global error, the
+    largest error-to-bound ratio and the worst block error."""
+    worst = [0.0, 0.0, 0.0]
+    for i, (pr, dp) in enumerate(zip(probs, dprobs)):
+        M, N = pr["M"], pr["N"]
+        want = oracle.qgemm(opA, opB, M, N, pr["K"], alpha, pr["A"], pr["lda"], pr["B"], pr["ldb"],
                             beta, pr["C"], pr["ldc"])
-        e = relfro(host(dp["C"]), want)
-        worst = max(worst, e)
-    assert worst <= bound, worst
-    return worst
+        p = dict(pr, opA=opA, opB=opB, alpha=alpha, beta=beta)
+        st = assert_parity(logical(host(dp["C"]), M, N), logical(want, M, N), split_error_bound(p, terms),
+                           SPLIT_BAR[terms], label=f"problem {i} ({M}x{N}x{pr['K']})", verbose=False)
+        worst = [max(a, b) for a, b in zip(worst, st)]
+    print(f"worst over {len(probs)} problems: rel err {worst[0]:.3e}, error / componentwise bound {worst[1]:.3e}, "
+          f"block rel err {worst[2]:.3e}")
+    return worst[0]
 
 
 @pytest.mark.parametrize("opA,opB", [("N", "N"), ("C", "T"), ("T", "R")])
@@ -51,6 +59,20 @@ def test_grouped_small(gpu, opA, opB):
     plan.run()
     worst = check_all(probs, dprobs, opA, opB, al, be)
     print(f"grouped {opA}{opB}: worst rel err {worst:.2e}, {plan.info()}")
+    plan.close()
+
+
+@pytest.mark.parametrize("terms", [3, 9])
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "C")])
+def test_grouped_split_terms(gpu, terms, opA, opB):
+    """The 3- and 9-product variants of the grouped kernel, each problem
+    against the oracle at the single-GEMM bars."""
+    probs = make_set(150, 1, 200, 200 + terms + len(opA + opB), opA, opB)
+    al, be = np.array([0.6, -0.2, 0.3, 0.1]), np.array([0.5, 0.1, -0.2, 0.3])
+    dprobs = to_dev(probs)
+    plan = q.GroupedPlan(dprobs, opA, opB, al, be, split_terms=terms)
+    plan.run()
+    check_all(probs, dprobs, opA, opB, al, be, terms)
     plan.close()
 
 
@@ -81,7 +103,9 @@ def test_grouped_empty_and_degenerate(gpu):
             continue
         want = oracle.qgemm("N", "N", pr["M"], pr["N"], pr["K"], al, pr["A"], pr["lda"], pr["B"], pr["ldb"],
                             be, pr["C"], pr["ldc"])
-        assert relfro(host(dp["C"])[:, :pr["M"]], want[:, :pr["M"]]) <= 1e-6, i
+        p = dict(pr, opA="N", opB="N", alpha=al, beta=be)
+        assert_parity(logical(host(dp["C"]), pr["M"], pr["N"]), logical(want, pr["M"], pr["N"]),
+                      split_error_bound(p), 1e-6, label=f"degenerate set, problem {i}")
     q.GroupedPlan([], "N", "N", al, be).run()
 
 
