@@ -12,7 +12,8 @@ multiply-add, 2 flops each).  Beside it the line carries:
                    HBM traffic from the committed rocprofv3 counter summary when
                    it was taken on the current kernel source;
   cpu_baseline  -- the CPU oracle timed on this host on a bounded column sample;
-  variants      -- the split-BF16 FP32 path, the grouped batched launch, the
+  variants      -- the split-BF16 FP32 path, the grouped batched launch (FP32
+                   and FP64), the
                    linear-layer forward + backward, the general scalar
                    placement, the Hermitian rank-k update, the triangular
                    multiply, the mixed-type products, the level-1/2
@@ -22,7 +23,7 @@ multiply-add, 2 flops each).  Beside it the line carries:
 Other modes (used to produce the committed profiles):
     python bench.py --calibrate-copy    one 1 GiB device copy, for counter scaling
     python bench.py --probe-ops         one launch per op pair at 2048, for per-kernel counters
-    python bench.py --only fp64|split|grouped|linear|scalars|herk|trmm|mixed|blas12|shard|context
+    python bench.py --only fp64|split|grouped|grouped_f64|linear|scalars|herk|trmm|mixed|blas12|shard|context
                                                    one part, no CPU baseline
     python bench.py --sweep                        FP64 sizes 1024..8192 x op pairs, one line each
 """
@@ -146,9 +147,44 @@ def oracle_single_thread():
     return out
 
 
+def oracle_all_cores():
+    """The oracle on all host threads at M = N = K = 64, 1024, 2048 and 4096
+    (op N/N): the whole 64^3 problem, and the first 128, 64 and 32 columns of
+    C at the larger sizes (each column is a full M x K by K product)."""
+    import oracle
+    out = {}
+    for n, ncols in ((64, 64), (1024, 128), (2048, 64), (4096, 32)):
+        p = W.gemm_problem(W.BASE_SEED + 7, n, n, n, "N", "N", dist="normal") if n <= 1024 else \
+            W.gemm_problem(W.BASE_SEED + 7, n, ncols, n, "N", "N", dist="normal")
+        reps = 20 if n == 64 else 1
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oracle.qgemm("N", "N", n, ncols, n, p["alpha"], p["A"], p["lda"], p["B"][:ncols], p["ldb"],
+                         p["beta"], p["C"][:ncols], p["ldc"])
+        dt = (time.perf_counter() - t0) / reps
+        out[f"{n}_cubed"] = {"gflops": round(q.flops(n, ncols, n) / dt / 1e9, 3), "columns": ncols,
+                             "seconds": round(dt, 4)}
+    return out
+
+
 def relfro(got, want):
     den = np.linalg.norm(want)
     return float(np.linalg.norm(np.asarray(got, np.float64) - want) / (den if den > 0 else 1.0))
+
+
+def sampled_error(p, Cdev, nrows, ncols, seed):
+    """Relative Frobenius error of a computed C (device, storage layout) against
+    the oracle on a seeded nrows x ncols sample of output entries (each entry
+    is the full K-term sum; the oracle computes only the sampled entries).
+    Returns (error, sample description)."""
+    import oracle
+    g = np.random.default_rng(seed)
+    rows = np.sort(g.choice(p["M"], min(nrows, p["M"]), replace=False))
+    cols = np.sort(g.choice(p["N"], min(ncols, p["N"]), replace=False))
+    want = oracle.qgemm_entries(p["opA"], p["opB"], p["K"], p["alpha"], p["A"], p["B"], p["beta"], p["C"],
+                                rows, cols)
+    got = Cdev[torch.from_numpy(cols).cuda()][:, torch.from_numpy(rows).cuda()].cpu().numpy()
+    return relfro(got, want), f"{len(rows)} x {len(cols)} entries (seeded)"
 
 
 def variant_split(steps, warmup):
@@ -227,6 +263,43 @@ def variant_grouped(steps, warmup):
                                   "bf16_mfma_utilization": round(6 * tf / PEAK_BF16, 4),
                                   "algorithmic_gbps": round(by / (ev * 1e-3) / 1e9, 1),
                                   "hbm_frac": round(by / (ev * 1e-3) / 1e9 / PEAK_HBM, 4),
+                                  "graph_replay": True, "work_items": info["work_items"],
+                                  "worst_rel_err_64_sampled_problems": float(f"{err:.3e}")}}
+
+
+def variant_grouped_f64(steps, warmup):
+    """The same 4096 problem sizes (M, N, K log-uniform in [8, 512], op N/N,
+    alpha = 1, beta = 0.5) in FP64 as one persistent launch of the FP64 tile,
+    replayed from a captured graph; error on 64 sampled problems (the first
+    replay's output)."""
+    import oracle
+    w = W.grouped(dtype=np.float64)
+    probs = [dict(pr, A=dev(pr["A"]), B=dev(pr["B"]), C=dev(pr["C"])) for pr in w["problems"]]
+    plan = q.GroupedPlan(probs, "N", "N", w["alpha"], w["beta"], dtype=torch.float64)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        plan.run()
+    graph.replay()
+    torch.cuda.synchronize()
+    g = np.random.default_rng(4)
+    sample = sorted(g.choice(len(probs), 64, replace=False))
+    err = 0.0
+    for i in sample:
+        pr = w["problems"][i]
+        want = oracle.qgemm("N", "N", pr["M"], pr["N"], pr["K"], w["alpha"], pr["A"], pr["lda"], pr["B"],
+                            pr["ldb"], w["beta"], pr["C"], pr["ldc"])
+        err = max(err, relfro(probs[i]["C"].cpu().numpy(), want))
+    wall, ev = time_launches(graph.replay, steps * 4, warmup)
+    fl = sum(q.flops(pr["M"], pr["N"], pr["K"]) for pr in w["problems"])
+    by = sum(32 * (pr["M"] * pr["K"] + pr["K"] * pr["N"] + 2 * pr["M"] * pr["N"]) for pr in w["problems"])
+    tf = fl / (ev * 1e-3) / 1e12
+    info = plan.info()
+    plan.close()
+    return {"grouped_4096_fp64": {"ms": round(ev, 3), "tflops_effective": round(tf, 2),
+                                  "frac_fp64_peak": round(tf / PEAK_FP64, 4),
+                                  "algorithmic_gbps": round(by / (ev * 1e-3) / 1e9, 1),
                                   "graph_replay": True, "work_items": info["work_items"],
                                   "worst_rel_err_64_sampled_problems": float(f"{err:.3e}")}}
 
@@ -515,24 +588,38 @@ def variant_context(steps, warmup):
 
 def sweep(steps, warmup):
     """FP64 qgemm_d over M = N = K in 1024..8192 and every op pair of N, T, C:
-    one JSON line per case (event time per launch and effective TFLOP/s);
+    one JSON line per case (event time per launch, effective TFLOP/s and the
+    relative Frobenius error of one launch's output against the oracle on a
+    seeded sample of entries: all of C at 1024, 256 x 128 entries above);
     sizes up to 2048 are timed over at least 50 launches after 10, in three
     such windows of which the median is reported (a one-off clock change
     during a sub-millisecond window would otherwise decide the figure)."""
+    import oracle
     for n in W.SWEEP_SIZES:
         for opA, opB in W.OP_PAIRS:
             p = W.gemm_sweep(n, opA, opB)
             A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
+            C0 = C.clone()
             # short launches need more of them for steady clocks
             st, wu, win = (max(steps, 50), max(warmup, 10), 3) if n <= 2048 else (steps, warmup, 1)
             evs = [time_launches(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
                                                    p["beta"], C, p["ldc"]), st, wu)[1] for _ in range(win)]
             ev = sorted(evs)[len(evs) // 2]
+            C.copy_(C0)                                   # one launch on the pristine C, checked
+            q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], C, p["ldc"])
+            torch.cuda.synchronize()
+            if n <= 1024:
+                want = oracle.qgemm(opA, opB, n, n, n, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"], p["beta"],
+                                    p["C"], p["ldc"])
+                err, sample = relfro(C.cpu().numpy(), want), "all entries"
+            else:
+                err, sample = sampled_error(p, C, 256, 128, seed=n + 7 * W.OP_PAIRS.index((opA, opB)))
             fl = q.flops(n, n, n)
             print(json.dumps({"sweep": f"{n} {opA}/{opB}", "ms": round(ev, 3),
                               "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
-                              "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4)}), flush=True)
-            del A, B, C
+                              "frac_fp64_peak": round(fl / (ev * 1e-3) / 1e12 / PEAK_FP64, 4),
+                              "rel_err_vs_oracle": float(f"{err:.3e}"), "err_sample": sample}), flush=True)
+            del A, B, C, C0
             torch.cuda.empty_cache()
 
 
@@ -581,8 +668,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--probe-ops", action="store_true", help="one launch per op pair at 2048 (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="time the FP64 size x op-pair sweep, one line per case")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12", "shard",
-                                       "context"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "grouped_f64", "linear", "scalars", "herk", "trmm",
+                                       "mixed", "blas12", "shard", "context"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -603,8 +690,10 @@ def main():
         sweep(args.steps, args.warmup)
         return
 
-    if args.only in ("split", "grouped", "linear", "scalars", "herk", "trmm", "mixed", "blas12", "shard", "context"):
-        fn = {"split": variant_split, "grouped": variant_grouped, "linear": variant_linear,
+    if args.only in ("split", "grouped", "grouped_f64", "linear", "scalars", "herk", "trmm", "mixed", "blas12",
+                     "shard", "context"):
+        fn = {"split": variant_split, "grouped": variant_grouped, "grouped_f64": variant_grouped_f64,
+              "linear": variant_linear,
               "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm,
               "mixed": variant_mixed, "blas12": variant_blas12, "shard": variant_shard,
               "context": variant_context}[args.only]
@@ -620,8 +709,16 @@ def main():
     def step():
         q.qgemm_d("N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n)
 
+    C0 = C.clone()
     log(f"[bench] timing {args.steps} steps after {args.warmup} warmup")
     wall_ms, ev_ms = time_launches(step, args.steps, args.warmup)
+    # after the timed region: one launch on the pristine C, checked against the oracle on sampled entries
+    C.copy_(C0)
+    step()
+    torch.cuda.synchronize()
+    del C0
+    log("[bench] checking the timed launch's output against the oracle")
+    head_err, head_sample = sampled_error(p, C, 256, 128, seed=8192)
     fl = q.flops(n, n, n)
     value = fl / (wall_ms * 1e-3) / 1e12
     achieved = fl / (ev_ms * 1e-3) / 1e12
@@ -644,6 +741,8 @@ def main():
                                "alpha/beta, A/B/C components U[-1,1] (seeded)",
                    "M": n, "N": n, "K": n, "opA": "N", "opB": "N",
                    "pct_of_fp64_matrix_peak": round(100 * value / PEAK_FP64, 2)},
+        "rel_err_vs_oracle_sampled": float(f"{head_err:.3e}"),
+        "err_sample": f"{head_sample} of C from one launch of the timed kernel on the same inputs",
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
                      "traffic": traffic, "kernel": "qgemm_f64_kernel<32,false,false,false,0>",
@@ -656,7 +755,8 @@ def main():
         return
     if not args.no_variants:
         variants = {}
-        for name, fn in (("split", variant_split), ("grouped", variant_grouped), ("linear", variant_linear),
+        for name, fn in (("split", variant_split), ("grouped", variant_grouped),
+                         ("grouped_f64", variant_grouped_f64), ("linear", variant_linear),
                          ("scalars", variant_scalars), ("herk", variant_herk), ("trmm", variant_trmm),
                          ("mixed", variant_mixed), ("blas12", variant_blas12), ("shard", variant_shard),
                          ("context", variant_context)):
@@ -676,6 +776,7 @@ def main():
         log(f"[bench] CPU oracle baseline on {ncols} columns")
         line["cpu_baseline"] = cpu_baseline(p, ncols)
         line["cpu_baseline"]["single_thread"] = oracle_single_thread()
+        line["cpu_baseline"]["all_cores_by_size"] = oracle_all_cores()
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

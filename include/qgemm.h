@@ -325,25 +325,32 @@ qgemm_status_t qgemv_s(int trans, int64_t M, int64_t N, const double *alpha, con
                        const float *x, int64_t incx, const double *beta, float *y, int64_t incy, void *stream);
 
 /*
- * Grouped (batched) FP32 quaternion GEMM: many independent problems
+ * Grouped (batched) quaternion GEMM: many independent problems
  *   C_i <- alpha op(A_i) op(B_i) + beta C_i,  i = 0..count-1,
- * with common ops, scalars and split, run as ONE persistent kernel launch
- * of the split-BF16 path.  This batching is an extension beyond the paper;
- * the tile shape of each problem is chosen per size class from a table
- * produced by the library's tile tuner (the analogue of the paper's
- * autotuned caching parameters, Sec. 5).
+ * (Sec. 3.1, Eq. general_gemm, for each problem) with common ops, scalars
+ * and element type, run as ONE persistent kernel launch.  This batching is
+ * an extension beyond the paper.
+ *   dtype QGEMM_DTYPE_F64: the arrays are double and every problem runs on
+ *     the FP64 tile of qgemm_d (same arithmetic; one tile class, 32 x 64
+ *     quaternions).  split_terms must be 0.
+ *   dtype QGEMM_DTYPE_F32: the arrays are float and every problem runs on
+ *     the split-BF16 tile of qgemm_s (split_terms as there).  The tile shape
+ *     of each problem is chosen per size class from a table produced by the
+ *     library's tile tuner (the analogue of the paper's autotuned caching
+ *     parameters, Sec. 5).
  *
- * qgemm_batched_plan_create: validates every problem (as qgemm_s does;
- *   on failure qgemm_last_invalid_arg() names the field -- 3 M, 4 N, 5 K,
- *   7 A, 8 lda, 9 B, 10 ldb, 12 C, 13 ldc -- and qgemm_last_invalid_problem()
- *   its index), builds the work table on the host and copies it to the
- *   current device (hipMalloc + synchronous copy: do NOT call it inside a
- *   stream capture).  tile_class < 0 uses the tuned table; 0..3 forces one
- *   class (0 = 32x64, 1 = 64x32, 2 = 32x32, 3 = 16x64 quaternions) for
- *   every problem.  The plan keeps the problem pointers and
- *   sizes: the buffers must stay valid while the plan is run.
- *   Arguments: 1 plan, 2 opA, 3 opB, 4 count, 5 problems, 6 alpha, 7 beta,
- *   8 split_terms, 9 tile_class.
+ * qgemm_batched_plan_create: validates every problem (as qgemm_d / qgemm_s
+ *   do; on failure qgemm_last_invalid_arg() names the field -- 3 M, 4 N,
+ *   5 K, 7 A, 8 lda, 9 B, 10 ldb, 12 C, 13 ldc, numbered as in those calls --
+ *   and qgemm_last_invalid_problem() its index), builds the work table on
+ *   the host and copies it to the current device (hipMalloc + synchronous
+ *   copy: do NOT call it inside a stream capture).  tile_class < 0 uses the
+ *   tuned table (FP32) or the one FP64 class; otherwise FP32 plans take
+ *   0..3 (0 = 32x64, 1 = 64x32, 2 = 32x32, 3 = 16x64 quaternions) and FP64
+ *   plans 0 (32x64) for every problem.  The plan keeps the problem pointers
+ *   and sizes: the buffers must stay valid while the plan is run.
+ *   Arguments: 1 plan, 2 dtype, 3 opA, 4 opB, 5 count, 6 problems, 7 alpha,
+ *   8 beta, 9 split_terms, 10 tile_class.
  * qgemm_batched_run: enqueues the single launch on `stream`.  It allocates
  *   nothing, copies nothing and does not synchronise, so it may be captured
  *   into a hipGraph and replayed.  Must run on the device the plan was made
@@ -352,6 +359,11 @@ qgemm_status_t qgemv_s(int trans, int64_t M, int64_t N, const double *alpha, con
  * qgemm_batched_plan_destroy: frees the plan's device tables (synchronises
  *   the device).
  */
+typedef enum {
+    QGEMM_DTYPE_F32 = 0,
+    QGEMM_DTYPE_F64 = 1
+} qgemm_dtype_t;
+
 typedef struct qgemm_problem_t {
     int64_t M, N, K;
     int64_t lda, ldb, ldc;
@@ -362,12 +374,13 @@ typedef struct qgemm_problem_t {
 
 typedef struct qgemm_plan_s *qgemm_plan_t;
 
-qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, int64_t count,
+qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int dtype, int opA, int opB, int64_t count,
                                          const qgemm_problem_t *problems, const double *alpha,
                                          const double *beta, int split_terms, int tile_class);
 qgemm_status_t qgemm_batched_run(qgemm_plan_t plan, void *stream);
 qgemm_status_t qgemm_batched_plan_destroy(qgemm_plan_t plan);
-/* Work items, grid size and tiles per class (array of 4) of a plan. */
+/* Work items, grid size and tiles per class (array of 4; FP64 plans use
+ * only the first) of a plan. */
 qgemm_status_t qgemm_batched_plan_info(qgemm_plan_t plan, int64_t *work_items, int *grid,
                                        int64_t *class_counts);
 /* Index of the problem that made the last plan creation on this thread fail, or -1. */

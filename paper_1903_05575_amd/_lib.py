@@ -64,8 +64,8 @@ _SIGNATURES = {
     "qdot_s": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp], _int),
     "qgemv_d": ([_int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemv_s": ([_int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
-    "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _i64, ctypes.POINTER(Problem), _dp, _dp,
-                                   _int, _int], _int),
+    "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _int, _i64, ctypes.POINTER(Problem), _dp,
+                                   _dp, _int, _int], _int),
     "qgemm_batched_run": ([_vp, _vp], _int),
     "qgemm_batched_plan_destroy": ([_vp], _int),
     "qgemm_batched_plan_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_int), ctypes.POINTER(_i64)], _int),
@@ -208,30 +208,37 @@ def qgemm_backward(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta,
 
 
 TILE_CLASSES = ((32, 64), (64, 32), (32, 32), (16, 64))
+DTYPES = {torch.float32: 0, torch.float64: 1}    # QGEMM_DTYPE_F32 / QGEMM_DTYPE_F64
 
 
 class GroupedPlan:
-    """A grouped (batched) FP32 quaternion GEMM plan (C-ABI
+    """A grouped (batched) quaternion GEMM plan (C-ABI
     qgemm_batched_plan_create / _run / _plan_destroy).
 
-    problems: sequence of dicts with float32 GPU tensors A, B, C and the ints
-    M, N, K, lda, ldb, ldc.  The tensors must outlive the plan; the plan keeps
-    references to them.  run() enqueues one persistent launch on the current
-    (or given) stream and may be captured in a CUDA/HIP graph."""
+    problems: sequence of dicts with GPU tensors A, B, C of `dtype` (float32:
+    split-BF16 path; float64: FP64 path) and the ints M, N, K, lda, ldb, ldc.
+    The tensors must outlive the plan; the plan keeps references to them.
+    run() enqueues one persistent launch on the current (or given) stream and
+    may be captured in a CUDA/HIP graph.  split_terms applies to float32
+    plans only."""
 
     def __init__(self, problems, opA="N", opB="N", alpha=(1, 0, 0, 0), beta=(0, 0, 0, 0), split_terms=6,
-                 tile_class=-1):
+                 tile_class=-1, dtype=torch.float32):
         self._handle = None
         self._keep = []
+        if dtype not in DTYPES:
+            raise ValueError(f"unsupported dtype {dtype}")
+        if dtype == torch.float64:
+            split_terms = 0
         arr = (Problem * max(1, len(problems)))()
         for i, pr in enumerate(problems):
             M, N, K = pr["M"], pr["N"], pr["K"]
             ra, ca = _stored(opA, M, K)
             rb, cb = _stored(opB, K, N)
             if M and N and K:
-                _check_storage(pr["A"], ra, ca, pr["lda"], torch.float32, f"problems[{i}].A")
-                _check_storage(pr["B"], rb, cb, pr["ldb"], torch.float32, f"problems[{i}].B")
-            _check_storage(pr["C"], M, N, pr["ldc"], torch.float32, f"problems[{i}].C")
+                _check_storage(pr["A"], ra, ca, pr["lda"], dtype, f"problems[{i}].A")
+                _check_storage(pr["B"], rb, cb, pr["ldb"], dtype, f"problems[{i}].B")
+            _check_storage(pr["C"], M, N, pr["ldc"], dtype, f"problems[{i}].C")
             arr[i] = Problem(M, N, K, pr["lda"], pr["ldb"], pr["ldc"],
                              pr["A"].data_ptr() if pr.get("A") is not None else None,
                              pr["B"].data_ptr() if pr.get("B") is not None else None,
@@ -240,8 +247,8 @@ class GroupedPlan:
         pa, _ka = _q4(alpha)
         pb, _kb = _q4(beta)
         h = ctypes.c_void_p()
-        rc = lib().qgemm_batched_plan_create(ctypes.byref(h), OPS[opA], OPS[opB], len(problems), arr, pa, pb,
-                                             int(split_terms), int(tile_class))
+        rc = lib().qgemm_batched_plan_create(ctypes.byref(h), DTYPES[dtype], OPS[opA], OPS[opB], len(problems),
+                                             arr, pa, pb, int(split_terms), int(tile_class))
         if rc != 0:
             bad = lib().qgemm_last_invalid_problem()
             raise QGemmError(rc, lib().qgemm_last_invalid_arg(), f"qgemm_batched_plan_create (problem {bad})")

@@ -784,7 +784,7 @@ struct qgemm_plan_s {
     qg::GroupedPlan *impl;
 };
 
-qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, int64_t count,
+qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int dtype, int opA, int opB, int64_t count,
                                          const qgemm_problem_t *problems, const double *alpha,
                                          const double *beta, int split_terms, int tile_class)
 {
@@ -792,18 +792,27 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
     g_bad_problem = -1;
     if (!plan) return fail(QGEMM_ERR_INVALID_ARG, 1);
     *plan = nullptr;
-    if (!valid_op(opA)) return fail(QGEMM_ERR_INVALID_ARG, 2);
-    if (!valid_op(opB)) return fail(QGEMM_ERR_INVALID_ARG, 3);
-    if (count < 0 || count > kMaxDim) return fail(QGEMM_ERR_INVALID_ARG, 4);
-    if (count > 0 && !problems) return fail(QGEMM_ERR_INVALID_ARG, 5);
-    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 6);
-    if (!beta) return fail(QGEMM_ERR_INVALID_ARG, 7);
-    if (split_terms == 0) split_terms = 6;
-    if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 8);
-    if (tile_class >= qg::kGroupedClasses) return fail(QGEMM_ERR_INVALID_ARG, 9);
+    if (dtype != QGEMM_DTYPE_F32 && dtype != QGEMM_DTYPE_F64) return fail(QGEMM_ERR_INVALID_ARG, 2);
+    const bool f64 = dtype == QGEMM_DTYPE_F64;
+    if (!valid_op(opA)) return fail(QGEMM_ERR_INVALID_ARG, 3);
+    if (!valid_op(opB)) return fail(QGEMM_ERR_INVALID_ARG, 4);
+    if (count < 0 || count > kMaxDim) return fail(QGEMM_ERR_INVALID_ARG, 5);
+    if (count > 0 && !problems) return fail(QGEMM_ERR_INVALID_ARG, 6);
+    if (!alpha) return fail(QGEMM_ERR_INVALID_ARG, 7);
+    if (!beta) return fail(QGEMM_ERR_INVALID_ARG, 8);
+    if (f64) {
+        if (split_terms != 0) return fail(QGEMM_ERR_INVALID_ARG, 9);   // FP64 plans do not split
+        if (tile_class >= qg::kGroupedClassesF64) return fail(QGEMM_ERR_INVALID_ARG, 10);
+    } else {
+        if (split_terms == 0) split_terms = 6;
+        if (split_terms != 3 && split_terms != 6 && split_terms != 9) return fail(QGEMM_ERR_INVALID_ARG, 9);
+        if (tile_class >= qg::kGroupedClasses) return fail(QGEMM_ERR_INVALID_ARG, 10);
+    }
+    const uintptr_t esz = f64 ? 32 : 16;   // bytes per quaternion
     for (int64_t i = 0; i < count; ++i) {
         const qgemm_problem_t &q = problems[i];
-        qgemm_status_t s = validate(opA, opB, q.M, q.N, q.K, alpha, q.A, q.lda, q.B, q.ldb, beta, q.C, q.ldc, 16, 16);
+        qgemm_status_t s = validate(opA, opB, q.M, q.N, q.K, alpha, q.A, q.lda, q.B, q.ldb, beta, q.C, q.ldc, esz,
+                                    (int64_t)esz);
         if (s != QGEMM_OK) {
             g_bad_problem = i;
             return s;
@@ -812,7 +821,7 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
     qg::GroupedPlan *impl = nullptr;
     int rc;
     try {   // host containers may throw; nothing crosses the C ABI
-        rc = qg::grouped_plan_create(&impl, op_transposes(opA), op_transposes(opB), op_conjugates(opA),
+        rc = qg::grouped_plan_create(&impl, f64, op_transposes(opA), op_transposes(opB), op_conjugates(opA),
                                      op_conjugates(opB), split_terms, alpha, beta, count, problems, tile_class);
     } catch (const std::bad_alloc &) {
         return QGEMM_ERR_ALLOC;
@@ -821,9 +830,9 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int opA, int opB, i
     }
     if (rc < 0) {
         g_bad_problem = -(int64_t)rc - 1;
-        return fail(QGEMM_ERR_UNSUPPORTED, 5);
+        return fail(QGEMM_ERR_UNSUPPORTED, 6);
     }
-    if (rc != QGEMM_OK) return fail((qgemm_status_t)rc, rc == QGEMM_ERR_UNSUPPORTED ? 5 : 0);
+    if (rc != QGEMM_OK) return fail((qgemm_status_t)rc, rc == QGEMM_ERR_UNSUPPORTED ? 6 : 0);
     qgemm_plan_s *h = new (std::nothrow) qgemm_plan_s{impl};
     if (!h) {
         qg::grouped_plan_destroy(impl);

@@ -139,12 +139,14 @@ template <typename T>
 hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A, int64_t lda, const T *x,
                         int64_t incx, const double *beta, T *y, int64_t incy, hipStream_t stream);
 
-// Grouped (batched) split-BF16 plans; see qgemm_grouped.hip.
+// Grouped (batched) plans, FP32 (split-BF16 tiles) or FP64; see qgemm_grouped.hip.
 struct GroupedPlan;
-constexpr int kGroupedClasses = 4;
+constexpr int kGroupedClasses = 4;      // tile classes of FP32 plans
+constexpr int kGroupedClassesF64 = 1;   // tile classes of FP64 plans
 int grouped_tile_class(int64_t M, int64_t N, int64_t K);
-int grouped_plan_create(GroupedPlan **out, bool ta, bool tb, bool ca, bool cb, int nterms, const double alpha[4],
-                        const double beta[4], int64_t count, const ::qgemm_problem_t *probs, int force_class);
+int grouped_plan_create(GroupedPlan **out, bool f64, bool ta, bool tb, bool ca, bool cb, int nterms,
+                        const double alpha[4], const double beta[4], int64_t count, const ::qgemm_problem_t *probs,
+                        int force_class);
 int grouped_plan_run(const GroupedPlan *pl, hipStream_t stream);
 void grouped_plan_destroy(GroupedPlan *pl);
 void grouped_plan_info(const GroupedPlan *pl, int64_t *nitems, int *grid, int64_t *class_count);

@@ -40,8 +40,8 @@ int main(void)
     expect("qgemm_backward_d lddc0", qgemm_backward_d(QGEMM_OP_N, QGEMM_OP_N, 4, 4, 4, one, A, 4, B, 4, C, 4, one,
                                                       NULL, 1, NULL, 1, A, 3, NULL), QGEMM_ERR_INVALID_ARG, 19);
     qgemm_plan_t plan = NULL;
-    expect("plan count", qgemm_batched_plan_create(&plan, QGEMM_OP_N, QGEMM_OP_N, -1, NULL, one, one, 6, -1),
-           QGEMM_ERR_INVALID_ARG, 4);
+    expect("plan count", qgemm_batched_plan_create(&plan, QGEMM_DTYPE_F64, QGEMM_OP_N, QGEMM_OP_N, -1, NULL, one,
+                                                   one, 0, -1), QGEMM_ERR_INVALID_ARG, 5);
     printf("dot workspace %d doubles\n", QGEMM_DOT_WORK_DOUBLES);
     return failures ? 1 : 0;
 }

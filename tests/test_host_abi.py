@@ -109,19 +109,46 @@ def test_batched_plan_validation(L):
         probs[i] = lb.Problem(4, 4, 4, 4, 4, 4, FAKE, FAKE_B, FAKE_C + 4096 * i)
     probs[1].ldb = 2
     h = ctypes.c_void_p()
-    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 0, 3, probs, ONE, ONE, 6, -1)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 10 and L.qgemm_last_invalid_problem() == 1
     probs[1].ldb = 4
     probs[2].C = FAKE + 4
-    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 0, 3, probs, ONE, ONE, 6, -1)
     assert rc == 2 and L.qgemm_last_invalid_arg() == 12 and L.qgemm_last_invalid_problem() == 2
-    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, 4)   # classes are 0..3
-    assert rc == 1 and L.qgemm_last_invalid_arg() == 9
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 0, 3, probs, ONE, ONE, 6, 4)   # classes are 0..3
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 10
     probs[2].C = FAKE_B + 64                     # C of problem 2 inside its B
-    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 3, probs, ONE, ONE, 6, -1)
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 0, 0, 0, 3, probs, ONE, ONE, 6, -1)
     assert rc == 1 and L.qgemm_last_invalid_arg() == 12 and L.qgemm_last_invalid_problem() == 2
     assert L.qgemm_batched_run(None, None) == 1
     assert L.qgemm_batched_plan_destroy(None) == 0
+
+
+def test_batched_plan_dtype_validation(L):
+    """dtype is argument 2 (QGEMM_DTYPE_F32 = 0, QGEMM_DTYPE_F64 = 1); FP64
+    plans take split_terms 0 and the one tile class 0, and ask FP64 alignment
+    (32 bytes) of every array."""
+    import paper_1903_05575_amd._lib as lb
+    probs = (lb.Problem * 2)()
+    for i in range(2):
+        probs[i] = lb.Problem(4, 4, 4, 4, 4, 4, FAKE, FAKE_B, FAKE_C + 4096 * i)
+    h = ctypes.c_void_p()
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 2, 0, 0, 2, probs, ONE, ONE, 0, -1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 2
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 1, 4, 0, 2, probs, ONE, ONE, 0, -1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 3
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 1, 0, 0, 2, probs, ONE, ONE, 6, -1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 9
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 1, 0, 0, 2, probs, ONE, ONE, 0, 1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 10
+    probs[1].A = FAKE + 16                       # one float quaternion: misaligned for double
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 1, 0, 0, 2, probs, ONE, ONE, 0, -1)
+    assert rc == 2 and L.qgemm_last_invalid_arg() == 7 and L.qgemm_last_invalid_problem() == 1
+    probs[1].A = FAKE
+    probs[0].lda = 3                             # M = 4 rows of A under op N
+    rc = L.qgemm_batched_plan_create(ctypes.byref(h), 1, 0, 0, 2, probs, ONE, ONE, 0, -1)
+    assert rc == 1 and L.qgemm_last_invalid_arg() == 8 and L.qgemm_last_invalid_problem() == 0
+    assert h.value is None
 
 
 def test_status_strings(L):
