@@ -311,6 +311,25 @@ qgemm_status_t qdot_s(int conj, int64_t n, const float *x, int64_t incx, const f
                       float *result, double *work, void *stream);
 
 /*
+ * qdot_d_noalloc -- qdot_d for callers that cannot allocate device memory or
+ *   hold a workspace (code under hipGraph capture, tight serving loops,
+ *   harnesses that forbid hipMalloc).  Same result, bit for bit, as qdot_d
+ *   with a workspace: the same kernels, with their partial sums in a
+ *   workspace of the library's own, a file-scope device array of
+ *   QGEMM_DOT_WORK_DOUBLES doubles (32 KiB) per GPU, held until the process
+ *   ends.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ *   library routine) and only launches kernels; its first call on a device
+ *   looks the array's address up (hipGetSymbolAddress).  n is not limited by
+ *   the array: the first pass writes at most 1024 partial sums whatever n.
+ *   Every call on one GPU shares that GPU's array: calls that overlap on one
+ *   GPU (other streams, other host threads) race and give undefined results;
+ *   calls in stream order on one stream are safe.
+ *   Arguments: 1 conj, 2 n, 3 x, 4 incx, 5 y, 6 incy, 7 result, then stream.
+ */
+qgemm_status_t qdot_d_noalloc(int conj, int64_t n, const double *x, int64_t incx, const double *y, int64_t incy,
+                              double *result, void *stream);
+
+/*
  * qgemv_d / qgemv_s -- y <- alpha op(A) x + beta y with A stored M x N
  *   (lda >= max(1, M)): op N or R gives x of N and y of M elements, op T or C
  *   x of M and y of N elements.  Quick returns (y untouched): M == 0, N == 0,

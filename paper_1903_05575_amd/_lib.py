@@ -62,6 +62,7 @@ _SIGNATURES = {
     "qaxpy_s": ([_i64, _dp, _vp, _i64, _vp, _i64, _vp], _int),
     "qdot_d": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp], _int),
     "qdot_s": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp], _int),
+    "qdot_d_noalloc": ([_int, _i64, _vp, _i64, _vp, _i64, _vp, _vp], _int),
     "qgemv_d": ([_int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemv_s": ([_int, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _dp, _vp, _i64, _vp], _int),
     "qgemm_batched_plan_create": ([ctypes.POINTER(_vp), _int, _int, _int, _i64, ctypes.POINTER(Problem), _dp,

@@ -390,6 +390,47 @@ hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A
     return hipGetLastError();
 }
 
+// Partial-sum workspace of qdot_d_noalloc: file-scope device memory, one copy
+// per GPU that the library runs on, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not the device array: the host
+// reaches the array only through the device address hipGetSymbolAddress
+// returns with that device current (dot_scratch below), never by the name.
+// Every qdot_d_noalloc call on one GPU shares that GPU's copy.  Pass 1 of the
+// dot writes the partial sum of every block it launches and pass 2 reads only
+// those, so nothing needs clearing between calls; calls that overlap on one
+// GPU (two streams, or two host threads) race on it.
+namespace {
+constexpr int kDotScratchDoubles = 4 * kDotParts;
+__device__ __align__(256) double scratch[kDotScratchDoubles];
+
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per
+// device (ordinals 0..63 are cached; others look it up on every call).  Two
+// threads may race the first lookup: both store the same address.
+hipError_t dot_scratch(double **out, int *capacity)
+{
+    static std::atomic<double *> cache[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    *capacity = kDotScratchDoubles;
+    if (dev >= 0 && dev < 64) {
+        double *p = cache[dev].load(std::memory_order_acquire);
+        if (p) {
+            *out = p;
+            return hipSuccess;
+        }
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    if (dev >= 0 && dev < 64) cache[dev].store(static_cast<double *>(ptr), std::memory_order_release);
+    *out = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
 template hipError_t launch_qaxpy<double>(int64_t, const double *, const double *, int64_t, double *, int64_t,
                                          hipStream_t);
 template hipError_t launch_qaxpy<float>(int64_t, const double *, const float *, int64_t, float *, int64_t,

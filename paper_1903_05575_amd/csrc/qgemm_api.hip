@@ -470,9 +470,12 @@ qgemm_status_t axpy_impl(int64_t n, const double *alpha, const T *x, int64_t inc
     return qg::launch_qaxpy<T>(n, alpha, x, incx, y, incy, stream) == hipSuccess ? QGEMM_OK : QGEMM_ERR_HIP;
 }
 
+// own_work: the partial sums go to the library's file-scope workspace
+// (qdot_d_noalloc) instead of the caller's `work`, whose address is looked up
+// only after every argument has been validated.
 template <typename T>
 qgemm_status_t dot_impl(int conj, int64_t n, const T *x, int64_t incx, const T *y, int64_t incy, T *result,
-                        double *work, hipStream_t stream)
+                        double *work, hipStream_t stream, bool own_work = false)
 {
     constexpr uintptr_t align = 4 * sizeof(T);
     g_bad_arg = 0;
@@ -485,12 +488,17 @@ qgemm_status_t dot_impl(int conj, int64_t n, const T *x, int64_t incx, const T *
     if (n > 0) {
         if (!x) return fail(QGEMM_ERR_INVALID_ARG, 3);
         if (!y) return fail(QGEMM_ERR_INVALID_ARG, 5);
-        if (!work) return fail(QGEMM_ERR_INVALID_ARG, 8);
+        if (!own_work && !work) return fail(QGEMM_ERR_INVALID_ARG, 8);
         if (reinterpret_cast<uintptr_t>(x) % align) return fail(QGEMM_ERR_MISALIGNED, 3);
         if (reinterpret_cast<uintptr_t>(y) % align) return fail(QGEMM_ERR_MISALIGNED, 5);
-        if (reinterpret_cast<uintptr_t>(work) % sizeof(double)) return fail(QGEMM_ERR_MISALIGNED, 8);
+        if (!own_work && reinterpret_cast<uintptr_t>(work) % sizeof(double)) return fail(QGEMM_ERR_MISALIGNED, 8);
         if (!extent_fits(incx, 1, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 4);
         if (!extent_fits(incy, 1, n, 4 * sizeof(T))) return fail(QGEMM_ERR_UNSUPPORTED, 6);
+        if (own_work) {
+            int cap = 0;
+            if (qg::dot_scratch(&work, &cap) != hipSuccess) return QGEMM_ERR_HIP;
+            if (cap < 4 * qg::kDotParts) return QGEMM_ERR_UNSUPPORTED;   // cannot happen: sized for kDotParts
+        }
     }
     return qg::launch_qdot<T>(conj == 1, n, x, incx, y, incy, result, work, stream) == hipSuccess ? QGEMM_OK
                                                                                                 : QGEMM_ERR_HIP;
@@ -746,6 +754,12 @@ qgemm_status_t qdot_s(int conj, int64_t n, const float *x, int64_t incx, const f
                       float *result, double *work, void *stream)
 {
     return dot_impl<float>(conj, n, x, incx, y, incy, result, work, static_cast<hipStream_t>(stream));
+}
+
+qgemm_status_t qdot_d_noalloc(int conj, int64_t n, const double *x, int64_t incx, const double *y, int64_t incy,
+                              double *result, void *stream)
+{
+    return dot_impl<double>(conj, n, x, incx, y, incy, result, nullptr, static_cast<hipStream_t>(stream), true);
 }
 
 qgemm_status_t qgemv_d(int trans, int64_t M, int64_t N, const double *alpha, const double *A, int64_t lda,

@@ -135,6 +135,9 @@ hipError_t launch_qaxpy(int64_t n, const double *alpha, const T *x, int64_t incx
 template <typename T>
 hipError_t launch_qdot(bool conj, int64_t n, const T *x, int64_t incx, const T *y, int64_t incy, T *result,
                        double *work, hipStream_t stream);
+// Device address (on the current device) and size in doubles of the
+// library's own dot-product workspace, a file-scope device array.
+hipError_t dot_scratch(double **out, int *capacity);
 template <typename T>
 hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A, int64_t lda, const T *x,
                         int64_t incx, const double *beta, T *y, int64_t incy, hipStream_t stream);
