@@ -225,6 +225,18 @@ def variant_split(steps, warmup):
                                               "rel_err_vs_oracle_sampled": float(f"{relfro(got64, want):.3e}")}
             out[key]["speedup_vs_fp64_path"] = round(ev64 / ev, 2)
             del A64, B64, C64
+            torch.cuda.empty_cache()
+            # vendor context: one BF16 product of the same real contraction, (4M x 4K) by (4K x N), as a
+            # hipBLASLt GEMM through torch.matmul; the split path runs six such products
+            X = torch.randn(4 * n, 4 * n, dtype=torch.bfloat16, device="cuda")
+            Y = torch.randn(4 * n, n, dtype=torch.bfloat16, device="cuda")
+            _, evv = time_launches(lambda: torch.matmul(X, Y), steps, warmup)
+            vendor = 2.0 * (4 * n) * (4 * n) * n / (evv * 1e-3) / 1e12
+            out["context_vendor_bf16_gemm_16384x4096x16384"] = {
+                "ms": round(evv, 3), "tflops_bf16": round(vendor, 1),
+                "frac_bf16_peak": round(vendor / PEAK_BF16, 4),
+                "split_path_bf16_rate_over_vendor": round(6 * tf / vendor, 3)}
+            del X, Y
         del A, B, C
         torch.cuda.empty_cache()
     return out
@@ -259,7 +271,12 @@ def variant_grouped(steps, warmup):
     tf = fl / (ev * 1e-3) / 1e12
     info = plan.info()
     plan.close()
+    table_txt = open(os.path.join(CSRC, "tile_table.inc")).read()
+    m_sha = re.search(r"kernel_source_sha:\s*(\w+)", table_txt)
+    tuned_sha = m_sha.group(1) if m_sha else None
+    kernel_sha = source_sha("qgemm_grouped.hip", "qgemm_bf16x3_tile.hpp", "qgemm_internal.hpp", "qgemm_device.hpp")
     return {"grouped_4096_fp32": {"ms": round(ev, 3), "tflops_effective": round(tf, 2),
+                                  "tile_table_tuned_on_current_kernel": tuned_sha == kernel_sha,
                                   "bf16_mfma_utilization": round(6 * tf / PEAK_BF16, 4),
                                   "algorithmic_gbps": round(by / (ev * 1e-3) / 1e9, 1),
                                   "hbm_frac": round(by / (ev * 1e-3) / 1e9 / PEAK_HBM, 4),
@@ -722,7 +739,7 @@ def main():
     fl = q.flops(n, n, n)
     value = fl / (wall_ms * 1e-3) / 1e12
     achieved = fl / (ev_ms * 1e-3) / 1e12
-    sha = source_sha("qgemm_f64.hip", "qgemm_internal.hpp", "qgemm_device.hpp")
+    sha = source_sha("qgemm_f64.hip", "qgemm_f64_tile.hpp", "qgemm_internal.hpp", "qgemm_device.hpp")
     traffic = read_traffic(f"qgemm_f64_{n}", sha)
     line = {
         "metric": METRIC,

@@ -406,6 +406,19 @@ qgemm_status_t qgemm_batched_plan_info(qgemm_plan_t plan, int64_t *work_items, i
 int64_t qgemm_last_invalid_problem(void);
 
 /*
+ * The tile table of FP32 plans: 32 tile classes (0..3) indexed
+ * [M bucket][N bucket][K bucket] (row-major, M and N buckets 1-16, 17-32,
+ * 33-64, 65+; K buckets 1-64, 65+).  The library's tuner (tune_tiles.py)
+ * compiles the table it finds into the library; qgemm_batched_set_tile_table
+ * installs another for the whole process (NULL restores the compiled-in one;
+ * an entry above 3 is QGEMM_ERR_INVALID_ARG, argument 1) and affects plans
+ * created afterwards; qgemm_batched_get_tile_table copies the table in effect
+ * into table[32].  Both are thread-safe.
+ */
+qgemm_status_t qgemm_batched_set_tile_table(const unsigned char *table);
+qgemm_status_t qgemm_batched_get_tile_table(unsigned char *table);
+
+/*
  * Gradient of the real loss L = sum_{mu,nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *     C = alpha op(A) op(B) + beta C0,

@@ -71,6 +71,8 @@ _SIGNATURES = {
     "qgemm_batched_plan_destroy": ([_vp], _int),
     "qgemm_batched_plan_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_int), ctypes.POINTER(_i64)], _int),
     "qgemm_last_invalid_problem": ([], _i64),
+    "qgemm_batched_set_tile_table": ([_vp], _int),
+    "qgemm_batched_get_tile_table": ([_vp], _int),
     "qgemm_backward_d": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _dp,
                           _vp, _i64, _vp, _i64, _vp, _i64, _vp], _int),
     "qgemm_backward_s": ([_int, _int, _i64, _i64, _i64, _dp, _vp, _i64, _vp, _i64, _vp, _i64, _dp,
@@ -210,6 +212,27 @@ def qgemm_backward(opA, opB, M, N, K, alpha, A, lda, B, ldb, G, ldg, beta,
 
 TILE_CLASSES = ((32, 64), (64, 32), (32, 32), (16, 64))
 DTYPES = {torch.float32: 0, torch.float64: 1}    # QGEMM_DTYPE_F32 / QGEMM_DTYPE_F64
+
+
+def tile_table():
+    """The tile table of FP32 grouped plans in effect, as a list of 32 classes
+    indexed [M bucket][N bucket][K bucket] (C-ABI qgemm_batched_get_tile_table)."""
+    buf = (ctypes.c_ubyte * 32)()
+    _raise(lib().qgemm_batched_get_tile_table(ctypes.cast(buf, _vp)), "qgemm_batched_get_tile_table")
+    return list(buf)
+
+
+def set_tile_table(table):
+    """Install a tile table for plans created afterwards (32 classes, or None
+    for the compiled-in table; C-ABI qgemm_batched_set_tile_table)."""
+    if table is None:
+        _raise(lib().qgemm_batched_set_tile_table(None), "qgemm_batched_set_tile_table")
+        return
+    table = list(table)
+    if len(table) != 32:
+        raise ValueError("a tile table has 32 entries")
+    buf = (ctypes.c_ubyte * 32)(*table)
+    _raise(lib().qgemm_batched_set_tile_table(ctypes.cast(buf, _vp)), "qgemm_batched_set_tile_table")
 
 
 class GroupedPlan:

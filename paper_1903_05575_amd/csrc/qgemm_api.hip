@@ -856,6 +856,24 @@ qgemm_status_t qgemm_batched_plan_create(qgemm_plan_t *plan, int dtype, int opA,
     return QGEMM_OK;
 }
 
+qgemm_status_t qgemm_batched_set_tile_table(const unsigned char *table)
+{
+    g_bad_arg = 0;
+    if (table)
+        for (int i = 0; i < qg::kTileTableCells; ++i)
+            if (table[i] >= qg::kGroupedClasses) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    qg::grouped_set_table(table);
+    return QGEMM_OK;
+}
+
+qgemm_status_t qgemm_batched_get_tile_table(unsigned char *table)
+{
+    g_bad_arg = 0;
+    if (!table) return fail(QGEMM_ERR_INVALID_ARG, 1);
+    qg::grouped_get_table(table);
+    return QGEMM_OK;
+}
+
 qgemm_status_t qgemm_batched_run(qgemm_plan_t plan, void *stream)
 {
     g_bad_arg = 0;

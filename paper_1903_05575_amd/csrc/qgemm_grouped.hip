@@ -25,7 +25,9 @@
 #include <new>
 #include <numeric>
 #include <queue>
+#include <cstring>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 namespace qg {
@@ -242,7 +244,34 @@ struct GroupedPlan {
     int64_t class_count[kClasses] = {};
 };
 
-int grouped_tile_class(int64_t M, int64_t N, int64_t K) { return kTileTable[bucket_mn(M)][bucket_mn(N)][bucket_k(K)]; }
+// The table in effect: the tuned one compiled in, or one installed at run
+// time (qgemm_batched_set_tile_table, the tuner's hook).  Guarded by a mutex;
+// plan creation reads it once per problem.
+namespace {
+std::mutex g_table_mutex;
+unsigned char g_table[4][4][2];
+bool g_table_custom = false;
+}  // namespace
+
+int grouped_tile_class(int64_t M, int64_t N, int64_t K)
+{
+    std::lock_guard<std::mutex> lk(g_table_mutex);
+    const int i = bucket_mn(M), j = bucket_mn(N), k = bucket_k(K);
+    return g_table_custom ? g_table[i][j][k] : kTileTable[i][j][k];
+}
+
+void grouped_set_table(const unsigned char *t)
+{
+    std::lock_guard<std::mutex> lk(g_table_mutex);
+    g_table_custom = t != nullptr;
+    if (t) memcpy(g_table, t, sizeof(g_table));
+}
+
+void grouped_get_table(unsigned char *t)
+{
+    std::lock_guard<std::mutex> lk(g_table_mutex);
+    memcpy(t, g_table_custom ? &g_table[0][0][0] : &kTileTable[0][0][0], sizeof(g_table));
+}
 
 // Tile geometry of class cls: FP64 plans have one class (32 x 64, K-tiles of
 // 4), FP32 plans the four split-BF16 classes.

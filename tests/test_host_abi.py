@@ -151,6 +151,35 @@ def test_batched_plan_dtype_validation(L):
     assert h.value is None
 
 
+def test_tile_table_get_set(L):
+    """The FP32 grouped tile table: read back what was installed, refuse an
+    entry above 3 (argument 1) without changing the table, restore with NULL."""
+    import paper_1903_05575_amd._lib as lb
+    built_in = lb.tile_table()
+    assert len(built_in) == 32 and all(0 <= c <= 3 for c in built_in)
+    custom = [(i * 7) % 4 for i in range(32)]
+    lb.set_tile_table(custom)
+    assert lb.tile_table() == custom
+    bad = (ctypes.c_ubyte * 32)(*([0] * 31 + [4]))
+    assert L.qgemm_batched_set_tile_table(ctypes.cast(bad, ctypes.c_void_p)) == 1
+    assert L.qgemm_last_invalid_arg() == 1
+    assert lb.tile_table() == custom
+    lb.set_tile_table(None)
+    assert lb.tile_table() == built_in
+    assert L.qgemm_batched_get_tile_table(None) == 1
+
+
+def test_tile_table_header_matches_tuner():
+    """tile_table.inc is what the tuner writes: 32 classes in 0..3 and the hash
+    of the kernel sources it was tuned on."""
+    import re as _re
+    txt = open(os.path.join(ROOT, "paper_1903_05575_amd", "csrc", "tile_table.inc")).read()
+    body = txt[txt.index("kTileTable"):]
+    vals = [int(v) for v in _re.findall(r"\b(\d)\b", body[body.index("=") + 1:])]
+    assert len(vals) == 32 and all(0 <= v <= 3 for v in vals)
+    assert _re.search(r"kernel_source_sha:\s*[0-9a-f]{16}", txt)
+
+
 def test_status_strings(L):
     for code, name in [(0, b"QGEMM_OK"), (1, b"QGEMM_ERR_INVALID_ARG"), (2, b"QGEMM_ERR_MISALIGNED"),
                        (3, b"QGEMM_ERR_HIP"), (4, b"QGEMM_ERR_ALLOC"), (5, b"QGEMM_ERR_UNSUPPORTED")]:
