@@ -119,7 +119,7 @@ __global__ __launch_bounds__(split::NT, kBlocksPerCU) void grouped_kernel(const 
         case 2: split::split_tile<T2, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 32, it.z * 32, nk, panel_tiles, lds); break;
         default: split::split_tile<T3, TA, TB, NTERMS, false, 1>(d, nullptr, it.y * 16, it.z * 64, nk, panel_tiles, lds); break;
         }
-        __syncthreads();                                 // LDS is reused by the next item
+        // no barrier here: the one-stage tile ends its K-loop on one, so every wave is done with LDS
     }
 }
 
