@@ -412,8 +412,9 @@ int64_t qgemm_last_invalid_problem(void);
  * compiles the table it finds into the library; qgemm_batched_set_tile_table
  * installs another for the whole process (NULL restores the compiled-in one;
  * an entry above 3 is QGEMM_ERR_INVALID_ARG, argument 1) and affects plans
- * created afterwards; qgemm_batched_get_tile_table copies the table in effect
- * into table[32].  Both are thread-safe.
+ * created afterwards (a plan copies the table in effect once, when it is
+ * created); qgemm_batched_get_tile_table copies the table in effect into
+ * table[32].  Both are thread-safe.
  */
 qgemm_status_t qgemm_batched_set_tile_table(const unsigned char *table);
 qgemm_status_t qgemm_batched_get_tile_table(unsigned char *table);

@@ -246,19 +246,12 @@ struct GroupedPlan {
 
 // The table in effect: the tuned one compiled in, or one installed at run
 // time (qgemm_batched_set_tile_table, the tuner's hook).  Guarded by a mutex;
-// plan creation reads it once per problem.
+// a plan takes one copy of it when it is created.
 namespace {
 std::mutex g_table_mutex;
 unsigned char g_table[4][4][2];
 bool g_table_custom = false;
 }  // namespace
-
-int grouped_tile_class(int64_t M, int64_t N, int64_t K)
-{
-    std::lock_guard<std::mutex> lk(g_table_mutex);
-    const int i = bucket_mn(M), j = bucket_mn(N), k = bucket_k(K);
-    return g_table_custom ? g_table[i][j][k] : kTileTable[i][j][k];
-}
 
 void grouped_set_table(const unsigned char *t)
 {
@@ -308,9 +301,11 @@ int grouped_plan_create(GroupedPlan **out, bool f64, bool ta, bool tb, bool ca, 
         pl->s.alpha[i] = alpha[i];
         pl->s.beta[i] = beta[i];
     }
+    unsigned char table[4][4][2];                // one consistent table for the whole plan
+    grouped_get_table(&table[0][0][0]);
     auto class_of = [&](const ::qgemm_problem_t &q) {
         if (f64) return 0;
-        return force_class >= 0 ? force_class : grouped_tile_class(q.M, q.N, q.K);
+        return force_class >= 0 ? force_class : (int)table[bucket_mn(q.M)][bucket_mn(q.N)][bucket_k(q.K)];
     };
     // count the tiles first: item indices and block starts are 32-bit on the device
     int64_t total_tiles = 0;

@@ -146,7 +146,6 @@ hipError_t launch_qgemv(int trans, int M, int N, const double *alpha, const T *A
 struct GroupedPlan;
 constexpr int kGroupedClasses = 4;      // tile classes of FP32 plans
 constexpr int kGroupedClassesF64 = 1;   // tile classes of FP64 plans
-int grouped_tile_class(int64_t M, int64_t N, int64_t K);
 constexpr int kTileTableCells = 32;     // [M bucket 4][N bucket 4][K bucket 2]
 void grouped_set_table(const unsigned char *t);   // nullptr: the compiled-in table
 void grouped_get_table(unsigned char *t);
