@@ -74,8 +74,8 @@ def workload(count=4096, lo=8, hi=512, seed=1903055750 + 3):
 
 
 def launch_time(probs, table, reps, alpha=(1.0, 0.0, 0.0, 0.0), beta=(0.5, 0.0, 0.0, 0.0)):
-    """Median-free single measurement: `reps` back-to-back launches of a plan
-    built with `table`, ms per launch (one warm-up launch first)."""
+    """One measurement: ms per launch over `reps` back-to-back launches of a
+    plan built with `table` (after one warm-up launch)."""
     _lib.set_tile_table(table)
     plan = _lib.GroupedPlan(probs, "N", "N", alpha, beta)
     plan.run()
