@@ -274,7 +274,8 @@ def variant_grouped(steps, warmup):
     table_txt = open(os.path.join(CSRC, "tile_table.inc")).read()
     m_sha = re.search(r"kernel_source_sha:\s*(\w+)", table_txt)
     tuned_sha = m_sha.group(1) if m_sha else None
-    kernel_sha = source_sha("qgemm_grouped.hip", "qgemm_bf16x3_tile.hpp", "qgemm_internal.hpp", "qgemm_device.hpp")
+    from paper_1903_05575_amd.tune_tiles import kernel_source_sha
+    kernel_sha = kernel_source_sha()
     return {"grouped_4096_fp32": {"ms": round(ev, 3), "tflops_effective": round(tf, 2),
                                   "tile_table_tuned_on_current_kernel": tuned_sha == kernel_sha,
                                   "bf16_mfma_utilization": round(6 * tf / PEAK_BF16, 4),

@@ -4,7 +4,8 @@
 //
 // Plan (host, outside any capture): every problem is cut into output tiles
 // whose shape is looked up per size class in the tuned tile table
-// (tile_table.inc); the (problem, tile) work items are sorted by cost
+// (tile_table.inc; FP64 problems all take the 32 x 64 FP64 tile); the
+// (problem, tile) work items are sorted by cost
 // (padded MFMA work + a fixed per-tile overhead) and dealt to the persistent
 // blocks longest-processing-time first, each block receiving a contiguous
 // run of the item array.  The block slots of the assignment are numbered so
@@ -21,13 +22,13 @@
 #include "../../include/qgemm.h"
 
 #include <algorithm>
+#include <cstring>
 #include <functional>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <queue>
-#include <cstring>
-#include <memory>
-#include <mutex>
 #include <vector>
 
 namespace qg {

@@ -29,6 +29,7 @@ reports whether the compiled table was tuned on the current kernel sources.
 import argparse
 import hashlib
 import os
+import re
 import sys
 import time
 
@@ -45,10 +46,20 @@ MN_EDGES = (16, 32, 64)
 K_EDGE = 64
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace runs collapsed, so that
+    an edit of a comment does not count as a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_sha():
+    """Hash of the code (not the comments) of the sources the grouped kernel
+    is built from, excluding the table itself."""
     h = hashlib.sha256()
     for n in KERNEL_SOURCES:
-        h.update(open(os.path.join(CSRC, n), "rb").read())
+        h.update(_code_only(open(os.path.join(CSRC, n)).read()).encode())
     return h.hexdigest()[:16]
 
 
