@@ -42,6 +42,8 @@ int main(void)
     qgemm_plan_t plan = NULL;
     expect("plan count", qgemm_batched_plan_create(&plan, QGEMM_DTYPE_F64, QGEMM_OP_N, QGEMM_OP_N, -1, NULL, one,
                                                    one, 0, -1), QGEMM_ERR_INVALID_ARG, 5);
+    expect("tile table NULL", qgemm_batched_get_tile_table(NULL), QGEMM_ERR_INVALID_ARG, 1);
+    expect("qdot_d_noalloc incx", qdot_d_noalloc(0, 4, A, 0, B, 1, C, NULL), QGEMM_ERR_INVALID_ARG, 4);
     printf("dot workspace %d doubles\n", QGEMM_DOT_WORK_DOUBLES);
     return failures ? 1 : 0;
 }

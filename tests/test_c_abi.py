@@ -24,4 +24,4 @@ def test_c_program_uses_the_abi(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "FAIL" not in r.stdout
-    assert r.stdout.count("ok ") == 12
+    assert r.stdout.count("ok ") == 14
