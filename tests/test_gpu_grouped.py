@@ -263,3 +263,31 @@ def test_grouped_f64_matches_single(gpu):
         q.qgemm_d("C", "N", pr["M"], pr["N"], pr["K"], al, dev(pr["A"]), pr["lda"], dev(pr["B"]), pr["ldb"], be,
                   C, pr["ldc"])
         np.testing.assert_array_equal(host(dp["C"]), host(C), err_msg=f"problem {i}")
+
+
+def test_grouped_runtime_tile_table(gpu):
+    """A table installed at run time (the tuner's hook) decides the classes of
+    plans created afterwards, and their results stay within the bounds; a plan
+    made before the change keeps its own classes."""
+    import paper_1903_05575_amd._lib as lb
+    probs = make_set(60, 1, 200, 61)
+    al, be = np.array([0.6, -0.2, 0.3, 0.1]), np.array([0.5, 0.1, -0.2, 0.3])
+    d_before = to_dev(probs)
+    before = q.GroupedPlan(d_before, "N", "N", al, be)
+    counts_before = before.info()["tiles_per_class"]
+    try:
+        for cls in range(len(q.TILE_CLASSES)):
+            lb.set_tile_table([cls] * 32)
+            dprobs = to_dev(probs)
+            plan = q.GroupedPlan(dprobs, "N", "N", al, be)
+            info = plan.info()
+            assert info["tiles_per_class"][cls] == info["work_items"], (cls, info)
+            plan.run()
+            check_all(probs, dprobs, "N", "N", al, be)
+            plan.close()
+    finally:
+        lb.set_tile_table(None)
+    assert before.info()["tiles_per_class"] == counts_before
+    before.run()
+    check_all(probs, d_before, "N", "N", al, be)
+    before.close()

@@ -396,3 +396,31 @@ def test_validation_mixed_s(L):
     assert L.qgemm_mixed_s(*args(2, 4, FAR_A + 4, FAR_B, FAR_C)) == 2 and L.qgemm_last_invalid_arg() == 9
     assert L.qgemm_mixed_s(*args(4, 1, FAR_A, FAR_B, FAR_C + 8)) == 2 and L.qgemm_last_invalid_arg() == 14
     assert L.qgemm_mixed_s(*args(1, 1, FAR_A, FAR_B, FAR_C)) == 1 and L.qgemm_last_invalid_arg() == 2
+
+
+def test_tile_table_threads(L):
+    """Concurrent installs and reads of the tile table from several host
+    threads: every read returns one of the tables installed, whole."""
+    import threading
+    import paper_1903_05575_amd._lib as lb
+    tables = [[c] * 32 for c in range(4)]
+    seen = []
+    errors = []
+
+    def worker(k):
+        try:
+            for i in range(200):
+                lb.set_tile_table(tables[(k + i) % 4])
+                t = lb.tile_table()
+                seen.append(tuple(t))
+        except Exception as e:          # noqa: BLE001 -- reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    lb.set_tile_table(None)
+    assert not errors
+    assert set(seen) <= {tuple(t) for t in tables}
