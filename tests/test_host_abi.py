@@ -424,3 +424,19 @@ def test_tile_table_threads(L):
     lb.set_tile_table(None)
     assert not errors
     assert set(seen) <= {tuple(t) for t in tables}
+
+
+def test_batched_plan_leading_dimension_limit(L):
+    """A problem whose leading dimension is beyond the 32-bit in-tile offsets
+    of its tile is refused when the plan is made (QGEMM_ERR_UNSUPPORTED,
+    argument 6 = the problem list, with its index), for FP32 and FP64 plans;
+    nothing is allocated before that check."""
+    import paper_1903_05575_amd._lib as lb
+    h = ctypes.c_void_p()
+    for dtype, big in ((0, 1 << 24), (1, 1 << 23)):
+        probs = (lb.Problem * 2)()
+        probs[0] = lb.Problem(4, 4, 4, 4, 4, 4, FAR_A, FAR_B, FAR_C)
+        probs[1] = lb.Problem(4, 4, 4, big, 4, 4, FAR_A + (1 << 36), FAR_B + (1 << 36), FAR_C + (1 << 36))
+        rc = L.qgemm_batched_plan_create(ctypes.byref(h), dtype, 1, 0, 2, probs, ONE, ONE, 0, -1)
+        assert rc == 5 and L.qgemm_last_invalid_arg() == 6 and L.qgemm_last_invalid_problem() == 1, (dtype, rc)
+        assert h.value is None
