@@ -81,12 +81,25 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def time_launches(fn, steps, warmup):
+def time_launches(fn, steps, warmup, min_ms=0.0):
     """Warm up, then time exactly `steps` calls.  Returns (wall ms per step,
-    event ms per step on the launch stream)."""
+    event ms per step on the launch stream).  With min_ms > 0 the warm-up is
+    extended to at least min_ms of launches and the timed region to at least
+    as many launches as fill min_ms: the GPU clock drops within a fraction of
+    a second of idling and takes tens of milliseconds to settle under a new
+    load, so a few launches of a short kernel would time the ramp."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if min_ms > 0:
+        t0, n = time.perf_counter(), 0
+        while (time.perf_counter() - t0) * 1e3 < min_ms:
+            fn()
+            n += 1
+            if n % 8 == 0:
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        steps = max(steps, int(np.ceil(min_ms / ((time.perf_counter() - t0) * 1e3 / n))))
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -98,6 +111,15 @@ def time_launches(fn, steps, warmup):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
     return wall, e0.elapsed_time(e1) / steps
+
+
+VARIANT_MIN_MS = 400.0
+
+
+def time_variant(fn, steps, warmup):
+    """time_launches for the secondary lines: at least VARIANT_MIN_MS of warm
+    launches and of timed launches (the headline times exactly --steps)."""
+    return time_launches(fn, steps, warmup, min_ms=VARIANT_MIN_MS)
 
 
 def cpu_baseline(p, ncols):
@@ -199,7 +221,7 @@ def variant_split(steps, warmup):
         p = W.gemm_precision(n, scaled=scaled)
         A, B = dev(p["A"]), dev(p["B"])
         C = torch.zeros((n, n, 4), dtype=torch.float32, device="cuda")
-        wall, ev = time_launches(lambda: q.qgemm_s("N", "C", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),
+        wall, ev = time_variant(lambda: q.qgemm_s("N", "C", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),
                                  steps, warmup)
         g = np.random.default_rng(11 + scaled)
         rows = np.sort(g.choice(n, 256, replace=False))
@@ -216,7 +238,7 @@ def variant_split(steps, warmup):
         if not scaled:
             A64, B64 = A.double(), B.double()
             C64 = torch.zeros((n, n, 4), dtype=torch.float64, device="cuda")
-            wall64, ev64 = time_launches(
+            wall64, ev64 = time_variant(
                 lambda: q.qgemm_d("N", "C", n, n, n, p["alpha"], A64, n, B64, n, p["beta"], C64, n),
                 max(1, steps // 2), 1)
             got64 = C64.cpu().numpy()[cols][:, rows]
@@ -230,7 +252,7 @@ def variant_split(steps, warmup):
             # hipBLASLt GEMM through torch.matmul; the split path runs six such products
             X = torch.randn(4 * n, 4 * n, dtype=torch.bfloat16, device="cuda")
             Y = torch.randn(4 * n, n, dtype=torch.bfloat16, device="cuda")
-            _, evv = time_launches(lambda: torch.matmul(X, Y), steps, warmup)
+            _, evv = time_variant(lambda: torch.matmul(X, Y), steps, warmup)
             vendor = 2.0 * (4 * n) * (4 * n) * n / (evv * 1e-3) / 1e12
             out["context_vendor_bf16_gemm_16384x4096x16384"] = {
                 "ms": round(evv, 3), "tflops_bf16": round(vendor, 1),
@@ -265,7 +287,7 @@ def variant_grouped(steps, warmup):
         want = oracle.qgemm("N", "N", pr["M"], pr["N"], pr["K"], w["alpha"], pr["A"], pr["lda"], pr["B"],
                             pr["ldb"], w["beta"], pr["C"], pr["ldc"])
         err = max(err, relfro(probs[i]["C"].cpu().numpy(), want))
-    wall, ev = time_launches(graph.replay, steps * 4, warmup)
+    wall, ev = time_variant(graph.replay, steps * 4, warmup)
     fl = sum(q.flops(pr["M"], pr["N"], pr["K"]) for pr in w["problems"])
     by = sum(16 * (pr["M"] * pr["K"] + pr["K"] * pr["N"] + 2 * pr["M"] * pr["N"]) for pr in w["problems"])
     tf = fl / (ev * 1e-3) / 1e12
@@ -309,7 +331,7 @@ def variant_grouped_f64(steps, warmup):
         want = oracle.qgemm("N", "N", pr["M"], pr["N"], pr["K"], w["alpha"], pr["A"], pr["lda"], pr["B"],
                             pr["ldb"], w["beta"], pr["C"], pr["ldc"])
         err = max(err, relfro(probs[i]["C"].cpu().numpy(), want))
-    wall, ev = time_launches(graph.replay, steps * 4, warmup)
+    wall, ev = time_variant(graph.replay, steps * 4, warmup)
     fl = sum(q.flops(pr["M"], pr["N"], pr["K"]) for pr in w["problems"])
     by = sum(32 * (pr["M"] * pr["K"] + pr["K"] * pr["N"] + 2 * pr["M"] * pr["N"]) for pr in w["problems"])
     tf = fl / (ev * 1e-3) / 1e12
@@ -343,8 +365,8 @@ def variant_linear(steps, warmup):
         layer.weight.grad = None
         layer(X).backward(dY)
 
-    _, ev_f = time_launches(fwd, steps, warmup)
-    _, ev_fb = time_launches(fwd_bwd, steps, warmup)
+    _, ev_f = time_variant(fwd, steps, warmup)
+    _, ev_fb = time_variant(fwd_bwd, steps, warmup)
     Y = fwd().detach().cpu().numpy()
     fwd_bwd()
     dX = X.grad.cpu().numpy()
@@ -377,9 +399,9 @@ def variant_scalars(steps, warmup):
     A, B = dev(p["A"]), dev(p["B"])
     C0 = dev(p["C"])
     C = C0.clone()
-    _, ev = time_launches(lambda: q.qgemm_ex("N", "N", n, n, n, aL, aM, aR, A, n, B, n, bL, bR, C, n), steps, warmup)
+    _, ev = time_variant(lambda: q.qgemm_ex("N", "N", n, n, n, aL, aM, aR, A, n, B, n, bL, bR, C, n), steps, warmup)
     C2 = C0.clone()
-    _, ev_d = time_launches(lambda: q.qgemm_d("N", "N", n, n, n, aL, A, n, B, n, bL, C2, n), steps, warmup)
+    _, ev_d = time_variant(lambda: q.qgemm_d("N", "N", n, n, n, aL, A, n, B, n, bL, C2, n), steps, warmup)
     C.copy_(C0)
     q.qgemm_ex("N", "N", n, n, n, aL, aM, aR, A, n, B, n, bL, bR, C, n)
     gs = np.random.default_rng(7)
@@ -407,7 +429,7 @@ def variant_herk(steps, warmup):
     C = W.qmatrix(g, n, n, dist="uniform")
     Ad, Cd0 = dev(A), dev(C)
     Cd = Cd0.clone()
-    _, ev = time_launches(lambda: q.qherk("L", "N", n, n, 1.0, Ad, n, 0.5, Cd, n), steps, warmup)
+    _, ev = time_variant(lambda: q.qherk("L", "N", n, n, 1.0, Ad, n, 0.5, Cd, n), steps, warmup)
     Cd.copy_(Cd0)
     q.qherk("L", "N", n, n, 1.0, Ad, n, 0.5, Cd, n)
     gs = np.random.default_rng(8)
@@ -432,7 +454,7 @@ def variant_trmm(steps, warmup):
     Ad, Bd = dev(t["A"]), dev(t["B"])
     Cd = torch.empty_like(Bd)
     al = t["alpha"]
-    _, ev = time_launches(lambda: q.qtrmm("L", "L", "N", "N", n, n, al, Ad, n, Bd, n, Cd, n), steps, warmup)
+    _, ev = time_variant(lambda: q.qtrmm("L", "L", "N", "N", n, n, al, Ad, n, Bd, n, Cd, n), steps, warmup)
     gs = np.random.default_rng(9)
     cols = np.sort(gs.choice(n, 16, replace=False))
     Bs = np.ascontiguousarray(t["B"][cols])
@@ -460,7 +482,7 @@ def variant_mixed(steps, warmup):
         p = dict(p, A=p["A"].astype(dt), B=p["B"].astype(dt), C=p["C"].astype(dt))
         A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
         C0 = C.clone()
-        _, ev = time_launches(lambda: q.qgemm_mixed(tA, tB, "N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),
+        _, ev = time_variant(lambda: q.qgemm_mixed(tA, tB, "N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n),
                               steps, warmup)
         C.copy_(C0)
         q.qgemm_mixed(tA, tB, "N", "N", n, n, n, p["alpha"], A, n, B, n, p["beta"], C, n)
@@ -500,7 +522,7 @@ def variant_blas12(steps, warmup):
                             ("N", np.float32, "fp32_gemv_8192_N")):
         A, x, y = dev(A64.astype(dt)), dev(x64.astype(dt)), dev(y64.astype(dt))
         y0 = y.clone()
-        _, ev = time_launches(lambda: q.qgemv(trans, M, N, al, A, M, x, 1, be, y, 1), steps, warmup)
+        _, ev = time_variant(lambda: q.qgemv(trans, M, N, al, A, M, x, 1, be, y, 1), steps, warmup)
         y.copy_(y0)
         q.qgemv(trans, M, N, al, A, M, x, 1, be, y, 1)
         want = oracle.qgemv(trans, M, N, al, A64.astype(dt), M, x64.astype(dt), 1, be, y64.astype(dt), 1)
@@ -514,7 +536,7 @@ def variant_blas12(steps, warmup):
     xs, ys = W.qvector(g, n), W.qvector(g, n)
     x, y = dev(xs), dev(ys)
     y0 = y.clone()
-    _, ev = time_launches(lambda: q.qaxpy(n, al, x, 1, y, 1), steps, warmup)
+    _, ev = time_variant(lambda: q.qaxpy(n, al, x, 1, y, 1), steps, warmup)
     y.copy_(y0)
     q.qaxpy(n, al, x, 1, y, 1)
     sl = slice(0, 1 << 16)
@@ -524,13 +546,13 @@ def variant_blas12(steps, warmup):
                              "rel_err_vs_oracle_first_65536": float(f"{relfro(y.cpu().numpy()[sl], want):.3e}")}
     res = torch.empty(4, dtype=torch.float64, device="cuda")
     work = torch.empty(q._lib.DOT_WORK_DOUBLES, dtype=torch.float64, device="cuda")
-    _, ev = time_launches(lambda: q.qdot(n, x, 1, y0, 1, conj=True, result=res, work=work), steps, warmup)
+    _, ev = time_variant(lambda: q.qdot(n, x, 1, y0, 1, conj=True, result=res, work=work), steps, warmup)
     want = oracle.qdot(True, n, xs, 1, ys, 1)
     out["fp64_dotc_2^26"] = {"ms": round(ev, 4), "algorithmic_gbps": round(64 * n / (ev * 1e-3) / 1e9, 1),
                              "hbm_frac": round(64 * n / (ev * 1e-3) / 8e12, 4),
                              "rel_err_vs_oracle": float(f"{relfro(res.cpu().numpy(), want):.3e}")}
     # achievable-bandwidth reference: a plain device copy of the same 2^26 quaternions
-    _, ev = time_launches(lambda: y0.copy_(x), steps, warmup)
+    _, ev = time_variant(lambda: y0.copy_(x), steps, warmup)
     out["reference_device_copy_2^26"] = {"ms": round(ev, 4), "gbps": round(64 * n / (ev * 1e-3) / 1e9, 1),
                                          "hbm_frac": round(64 * n / (ev * 1e-3) / 8e12, 4)}
     del x, y, y0
@@ -544,7 +566,7 @@ def variant_shard(steps, warmup):
     M, N, K = 1024, 8192, 8192
     p = W.gemm_problem(W.BASE_SEED + 30, M, N, K, "N", "N")
     A, B, C = dev(p["A"]), dev(p["B"]), dev(p["C"])
-    _, ev = time_launches(lambda: q.qgemm_d("N", "N", M, N, K, p["alpha"], A, M, B, K, p["beta"], C, M), steps,
+    _, ev = time_variant(lambda: q.qgemm_d("N", "N", M, N, K, p["alpha"], A, M, B, K, p["beta"], C, M), steps,
                           warmup)
     fl = q.flops(M, N, K)
     return {"fp64_row_shard_1024x8192x8192": {"ms": round(ev, 3), "tflops_effective": round(fl / (ev * 1e-3) / 1e12, 2),
@@ -571,7 +593,7 @@ def variant_context(steps, warmup):
             z1 = torch.complex(S[..., 2], S[..., 3]).T
             return torch.cat([torch.cat([z0, z1], 1), torch.cat([-z1.conj(), z0.conj()], 1)], 0).contiguous()
         Ac, Bc = cblock(A), cblock(B)
-        _, ev = time_launches(lambda: torch.matmul(Ac, Bc), steps, warmup)
+        _, ev = time_variant(lambda: torch.matmul(Ac, Bc), steps, warmup)
         Cc = torch.matmul(Ac, Bc)
         rows, cols = np.arange(0, n, n // 16), np.arange(3, n, n // 16)
         want = oracle.qgemm_entries("N", "N", n, one, p["A"], p["B"], zero, p["C"], rows, cols)   # (cols, rows, 4)
@@ -592,7 +614,7 @@ def variant_context(steps, warmup):
         AL = (Al[:, :, idx] * sign).permute(0, 2, 1, 3).reshape(4 * n, 4 * n).contiguous()   # (M, r, K, c)
         Br = B.reshape(n, 4 * n).T.contiguous()                                           # (4K, N)
         del Al
-        _, ev = time_launches(lambda: torch.matmul(AL, Br), steps, warmup)
+        _, ev = time_variant(lambda: torch.matmul(AL, Br), steps, warmup)
         Cr = torch.matmul(AL, Br).reshape(n, 4, n)                                       # (M, r, N)
         got = Cr[rows][:, :, cols].permute(2, 0, 1).cpu().numpy()                         # (cols, rows, 4)
         out["context_rocblas_dgemm_L_embedding_8192"] = {
@@ -620,7 +642,7 @@ def sweep(steps, warmup):
             C0 = C.clone()
             # short launches need more of them for steady clocks
             st, wu, win = (max(steps, 50), max(warmup, 10), 3) if n <= 2048 else (steps, warmup, 1)
-            evs = [time_launches(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
+            evs = [time_variant(lambda: q.qgemm_d(opA, opB, n, n, n, p["alpha"], A, p["lda"], B, p["ldb"],
                                                    p["beta"], C, p["ldc"]), st, wu)[1] for _ in range(win)]
             ev = sorted(evs)[len(evs) // 2]
             C.copy_(C0)                                   # one launch on the pristine C, checked
@@ -664,6 +686,75 @@ def probe_ops(n=2048):
             log(f"qgemm_mixed {ta}x{tb} {oa}/{ob} n={n}")
 
 
+def smi_reading():
+    """Socket power (W), GFX clock (MHz) and the board power cap (W) as the
+    system management tools report them now (None where they report none)."""
+    import subprocess
+    out = {"socket_power_w": None, "gfx_clk_mhz": None, "power_cap_w": None}
+    try:
+        r = subprocess.run(["amd-smi", "metric", "--json"], capture_output=True, text=True, timeout=30)
+        d, _ = json.JSONDecoder().raw_decode(r.stdout[r.stdout.index("{"):])
+        g = d["gpu_data"][0] if "gpu_data" in d else d[0]
+        out["socket_power_w"] = g["power"]["socket_power"]["value"]
+        out["gfx_clk_mhz"] = g["clock"]["gfx_0"]["clk"]["value"]
+    except (OSError, ValueError, KeyError, IndexError, TypeError, subprocess.SubprocessError):
+        pass
+    try:
+        r = subprocess.run(["rocm-smi", "-M", "--json"], capture_output=True, text=True, timeout=30)
+        d, _ = json.JSONDecoder().raw_decode(r.stdout[r.stdout.index("{"):])
+        out["power_cap_w"] = float(next(iter(d.values()))["Max Graphics Package Power (W)"])
+    except (OSError, ValueError, KeyError, StopIteration, TypeError, subprocess.SubprocessError):
+        pass
+    return out
+
+
+def power_probe(seconds=12.0):
+    """Each of three kernels kept busy for `seconds` of back-to-back launches:
+    FP64 qgemm_d at 8192^3 N/N, the split-BF16 qgemm_s at 4096^3 N/C, and the
+    vendor BF16 GEMM (hipBLASLt through torch.matmul) on one product of the
+    split path's real contraction (16384 x 16384 by 16384 x 4096).  Half-way
+    through, the socket power and GFX clock are read from amd-smi; one JSON
+    line per kernel with the sustained rate beside them."""
+    import threading
+    n64, n32 = 8192, 4096
+    cases = []
+    p = W.gemm_sweep(n64, "N", "N")
+    A64, B64, C64 = dev(p["A"]), dev(p["B"]), dev(p["C"])
+    cases.append(("qgemm_d 8192^3 N/N (FP64 MFMA)", q.flops(n64, n64, n64), "TFLOP/s effective",
+                  lambda: q.qgemm_d("N", "N", n64, n64, n64, p["alpha"], A64, n64, B64, n64, p["beta"], C64, n64)))
+    ps = W.gemm_precision(n32)
+    A32, B32 = dev(ps["A"]), dev(ps["B"])
+    C32 = torch.zeros((n32, n32, 4), dtype=torch.float32, device="cuda")
+    cases.append(("qgemm_s 4096^3 N/C (split BF16, 6 products)", q.flops(n32, n32, n32), "TFLOP/s effective",
+                  lambda: q.qgemm_s("N", "C", n32, n32, n32, ps["alpha"], A32, n32, B32, n32, ps["beta"], C32, n32)))
+    X = torch.randn(4 * n32, 4 * n32, dtype=torch.bfloat16, device="cuda")
+    Y = torch.randn(4 * n32, n32, dtype=torch.bfloat16, device="cuda")
+    cases.append(("vendor BF16 GEMM 16384x16384 by 16384x4096", 2.0 * (4 * n32) ** 2 * n32, "TFLOP/s BF16",
+                  lambda: torch.matmul(X, Y)))
+    for name, fl, unit, fn in cases:
+        fn()
+        torch.cuda.synchronize()
+        reading = {}
+        th = threading.Timer(seconds / 2, lambda: reading.update(smi_reading()))
+        t0, cnt = time.perf_counter(), 0
+        th.start()
+        while time.perf_counter() - t0 < seconds:
+            for _ in range(4):
+                fn()
+            torch.cuda.synchronize()
+            cnt += 4
+        dt = time.perf_counter() - t0
+        th.join()
+        rate = fl * cnt / dt / 1e12
+        line = {"power": name, "launches": cnt, "ms": round(dt / cnt * 1e3, 3), "rate": round(rate, 1),
+                "unit": unit, **reading}
+        # matrix-core work issued: the split path runs six BF16 products per effective flop
+        line["matrix_tflops"] = round(rate * (6 if "split" in name else 1), 1)
+        if reading.get("socket_power_w"):
+            line["matrix_tflops_per_w"] = round(line["matrix_tflops"] / reading["socket_power_w"], 3)
+        print(json.dumps(line), flush=True)
+
+
 def calibrate_copy():
     n = 1 << 30
     x = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -684,6 +775,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--power", action="store_true",
+                    help="sustained rate, socket power and clock of the FP64, split and vendor BF16 GEMMs")
     ap.add_argument("--probe-ops", action="store_true", help="one launch per op pair at 2048 (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="time the FP64 size x op-pair sweep, one line per case")
     ap.add_argument("--only", choices=["fp64", "split", "grouped", "grouped_f64", "linear", "scalars", "herk", "trmm",
@@ -698,6 +791,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     q.lib()
+    if args.power:
+        power_probe()
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return
