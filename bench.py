@@ -709,12 +709,13 @@ def smi_reading():
 
 
 def power_probe(seconds=12.0):
-    """Each of three kernels kept busy for `seconds` of back-to-back launches:
-    FP64 qgemm_d at 8192^3 N/N, the split-BF16 qgemm_s at 4096^3 N/C, and the
+    """Each of four kernels kept busy for `seconds` of back-to-back launches:
+    FP64 qgemm_d at 8192^3 N/N, the split-BF16 qgemm_s at 4096^3 N/C, the
     vendor BF16 GEMM (hipBLASLt through torch.matmul) on one product of the
-    split path's real contraction (16384 x 16384 by 16384 x 4096).  Half-way
-    through, the socket power and GFX clock are read from amd-smi; one JSON
-    line per kernel with the sustained rate beside them."""
+    split path's real contraction (16384 x 16384 by 16384 x 4096), and the
+    4096-problem FP32 batched launch (graph replays).  Half-way through, the
+    socket power and GFX clock are read from amd-smi; one JSON line per
+    kernel with the sustained rate beside them."""
     import threading
     n64, n32 = 8192, 4096
     cases = []
@@ -731,6 +732,17 @@ def power_probe(seconds=12.0):
     Y = torch.randn(4 * n32, n32, dtype=torch.bfloat16, device="cuda")
     cases.append(("vendor BF16 GEMM 16384x16384 by 16384x4096", 2.0 * (4 * n32) ** 2 * n32, "TFLOP/s BF16",
                   lambda: torch.matmul(X, Y)))
+    w = W.grouped()
+    probs = [dict(pr, A=dev(pr["A"]), B=dev(pr["B"]), C=dev(pr["C"])) for pr in w["problems"]]
+    plan = q.GroupedPlan(probs, "N", "N", w["alpha"], w["beta"])
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        plan.run()
+    cases.append(("batched FP32, 4096 problems (split BF16, 6 products)",
+                  sum(q.flops(pr["M"], pr["N"], pr["K"]) for pr in w["problems"]), "TFLOP/s effective",
+                  graph.replay))
     for name, fl, unit, fn in cases:
         fn()
         torch.cuda.synchronize()
@@ -748,11 +760,12 @@ def power_probe(seconds=12.0):
         rate = fl * cnt / dt / 1e12
         line = {"power": name, "launches": cnt, "ms": round(dt / cnt * 1e3, 3), "rate": round(rate, 1),
                 "unit": unit, **reading}
-        # matrix-core work issued: the split path runs six BF16 products per effective flop
-        line["matrix_tflops"] = round(rate * (6 if "split" in name else 1), 1)
+        # matrix-core work: six BF16 products per effective flop on the split paths (tile padding not counted)
+        line["matrix_tflops"] = round(rate * (6 if "6 products" in name else 1), 1)
         if reading.get("socket_power_w"):
             line["matrix_tflops_per_w"] = round(line["matrix_tflops"] / reading["socket_power_w"], 3)
         print(json.dumps(line), flush=True)
+    plan.close()
 
 
 def calibrate_copy():
@@ -776,7 +789,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--power", action="store_true",
-                    help="sustained rate, socket power and clock of the FP64, split and vendor BF16 GEMMs")
+                    help="sustained rate, socket power and clock of the FP64, split, vendor BF16 and batched GEMMs")
     ap.add_argument("--probe-ops", action="store_true", help="one launch per op pair at 2048 (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="time the FP64 size x op-pair sweep, one line per case")
     ap.add_argument("--only", choices=["fp64", "split", "grouped", "grouped_f64", "linear", "scalars", "herk", "trmm",
