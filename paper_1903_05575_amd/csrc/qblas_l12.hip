@@ -159,8 +159,9 @@ __global__ __launch_bounds__(NT) void qdot_final_kernel(int parts, const double 
 // columns in flight), then the column groups are summed in order
 // g = 0, 1, ... in LDS.  The GR rows of one column are 512 contiguous bytes
 // (FP64, 16 rows) or 128 (FP32, 8 rows).  Measured at 8192 x 8192: 8 columns
-// in flight is best for FP64, 4 for FP32 (8 was 30% slower); 8-row FP32
-// blocks (twice as many blocks in flight) took 0.233 -> 0.197 ms; more
+// in flight is best for FP64, 4 for FP32; 8-row FP32 blocks beat 16-row ones
+// (twice as many blocks in flight) and 4- or 2-row ones (0.213 against 0.239
+// and 0.291 ms, even with the blocks of one 128-byte line on one XCD); more
 // threads per block were slower for both.
 template <typename T>
 struct GemvN {
