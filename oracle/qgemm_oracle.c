@@ -24,8 +24,8 @@
  *
  * op codes: 0 = N (as stored), 1 = T (transpose, no conjugation),
  *           2 = C (conjugate transpose), 3 = R (conjugate, no transpose).
- * The T/C reading of op() and the R op used by the gradient are readings of
- * this build, not the paper's (the paper defines only ^T and ^H on matrices).
+ * The T/C reading of op() and the R op used by the gradient are readings
+ * chosen here, not the paper's (the paper defines only ^T and ^H on matrices).
  *
  * Parity pins for every function live in tests/test_oracle_pins.py.
  */
@@ -107,7 +107,7 @@ static double *materialise_op(int op, int64_t rows, int64_t cols,
  * C from the left.  Loop order follows Alg. 1 (reference GEMM): columns nu of C
  * outermost, then kappa, then the rows mu of the column.  Columns are
  * independent, so they are split over OpenMP threads.
- * Semantics this build chooses where the paper is silent (the BLAS
+ * Semantics chosen here where the paper is silent (the BLAS
  * convention): when beta is exactly zero (all four components) the old C is
  * not read, so NaN/Inf in C do not propagate; when alpha is exactly zero or
  * K == 0 the product is not formed and A, B are not read, giving C <- beta C.
@@ -427,7 +427,7 @@ int oracle_qgemv(int trans, int64_t M, int64_t N, const double *alpha, const dou
 /* Gradient of the real loss L = sum_{mu nu} <G_{mu nu}, C_{mu nu}> (the
  * Euclidean inner product of the four components) for
  *   C = alpha op(A) op(B) + beta C0.
- * Derivation (a reading of this build; the paper has no gradient): for one
+ * Derivation (a reading chosen here; the paper has no gradient): for one
  * term, <g, alpha a b> = Re(conj(g) alpha a b) is linear in a and in b, and
  * cycling the real part gives
  *   dL/d op(A)_{mu k} = sum_nu  conj(alpha) G_{mu nu} conj(op(B)_{k nu})
