@@ -631,9 +631,9 @@ def sweep(steps, warmup):
     one JSON line per case (event time per launch, effective TFLOP/s and the
     relative Frobenius error of one launch's output against the oracle on a
     seeded sample of entries: all of C at 1024, 256 x 128 entries above);
-    sizes up to 2048 are timed over at least 50 launches after 10, in three
-    such windows of which the median is reported (a one-off clock change
-    during a sub-millisecond window would otherwise decide the figure)."""
+    every case is timed over at least 0.4 s of launches after 0.4 s of warm
+    launches, and sizes up to 2048 in three such windows of which the median
+    is reported (a one-off clock change would otherwise decide the figure)."""
     import oracle
     for n in W.SWEEP_SIZES:
         for opA, opB in W.OP_PAIRS:
