@@ -46,7 +46,7 @@ MN_EDGES = (16, 32, 64)
 K_EDGE = 64
 
 
-def _code_only(text):
+def code_only(text):
     """Source text without comments and with whitespace runs collapsed, so that
     an edit of a comment does not count as a change of the kernel."""
     text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
@@ -59,7 +59,7 @@ def kernel_source_sha():
     is built from, excluding the table itself."""
     h = hashlib.sha256()
     for n in KERNEL_SOURCES:
-        h.update(_code_only(open(os.path.join(CSRC, n)).read()).encode())
+        h.update(code_only(open(os.path.join(CSRC, n)).read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -49,3 +49,11 @@ def test_smi_reading_with_unexpected_output(monkeypatch):
     outs = {"amd-smi": "no devices found\n", "rocm-smi": json.dumps({"card0": {}})}
     monkeypatch.setattr(subprocess, "run", _fake_run(outs))
     assert bench.smi_reading() == {"socket_power_w": None, "gfx_clk_mhz": None, "power_cap_w": None}
+
+
+def test_fp64_traffic_profile_taken_on_current_kernel():
+    """The headline's HBM traffic comes from the committed counter summary only
+    while that summary was taken on the current FP64 kernel code; this fails
+    when the kernel changes and the counters have not been taken again."""
+    t = bench.read_traffic("qgemm_f64_8192", bench.source_sha(*bench.FP64_SOURCES))
+    assert t is not None and 8.59e9 < t < 1e12
