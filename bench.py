@@ -348,6 +348,47 @@ def variant_grouped_f64(steps, warmup):
                                   "worst_rel_err_64_sampled_problems": float(f"{err:.3e}")}}
 
 
+def variant_grouped_kscan(steps, warmup):
+    """Cost model of the FP32 batched launch: the 4096 problems' M and N with
+    K forced to 16, 32, 64 and 128 (1, 2, 4, 8 K-tiles of 16 per item), and
+    with their own K; time per graph replay and the item and K-tile counts
+    of each plan.  The slope is the cost of one K-tile over all items, the
+    intercept the per-item cost (descriptor, first K-tile, epilogue)."""
+    from paper_1903_05575_amd import _lib
+    from paper_1903_05575_amd.tune_tiles import cell_of
+    mnk = W.grouped_sizes()
+    g = W.rng(W.BASE_SEED + 40)
+    out = {}
+    for kfix in (None, 16, 32, 64, 128):
+        probs = []
+        for M, N, K in mnk:
+            M, N, K = int(M), int(N), int(K) if kfix is None else kfix
+            probs.append(dict(M=M, N=N, K=K, lda=M, ldb=K, ldc=M, A=dev(W.qmatrix(g, M, K, dtype=np.float32)),
+                              B=dev(W.qmatrix(g, K, N, dtype=np.float32)),
+                              C=torch.zeros((N, M, 4), dtype=torch.float32, device="cuda")))
+        plan = q.GroupedPlan(probs, "N", "N", (1.0, 0.0, 0.0, 0.0), (0.5, 0.0, 0.0, 0.0))
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            plan.run()
+        _, ev = time_variant(graph.replay, steps * 4, warmup)
+        info = plan.info()
+        plan.close()
+        # K-tiles walked: ceil(K / 16) per item of the problem (every class walks K-tiles of 16)
+        table = _lib.tile_table()
+        ktiles = 0
+        for pr in probs:
+            cell = cell_of(pr["M"], pr["N"], pr["K"])
+            bm, bn = _lib.TILE_CLASSES[table[cell]]
+            ktiles += -(-pr["M"] // bm) * -(-pr["N"] // bn) * -(-pr["K"] // 16)
+        out["K=" + ("own" if kfix is None else str(kfix))] = {"ms": round(ev, 4), "work_items": info["work_items"],
+                                                               "k_tiles": ktiles}
+        del probs, graph
+        torch.cuda.empty_cache()
+    return {"grouped_4096_fp32_k_scan": out}
+
+
 def variant_linear(steps, warmup):
     """Quaternion linear layer Y = X W, X 8192 x 1024, W 1024 x 1024 (FP32,
     Glorot), forward + hand-written backward (dX, dW) through torch.autograd;
@@ -796,8 +837,8 @@ def main():
                     help="sustained rate, socket power and clock of the FP64, split, vendor BF16 and batched GEMMs")
     ap.add_argument("--probe-ops", action="store_true", help="one launch per op pair at 2048 (for counter runs)")
     ap.add_argument("--sweep", action="store_true", help="time the FP64 size x op-pair sweep, one line per case")
-    ap.add_argument("--only", choices=["fp64", "split", "grouped", "grouped_f64", "linear", "scalars", "herk", "trmm",
-                                       "mixed", "blas12", "shard", "context"],
+    ap.add_argument("--only", choices=["fp64", "split", "grouped", "grouped_f64", "grouped_kscan", "linear", "scalars",
+                                       "herk", "trmm", "mixed", "blas12", "shard", "context"],
                     help="run one part only and print its figures (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -821,9 +862,10 @@ def main():
         sweep(args.steps, args.warmup)
         return
 
-    if args.only in ("split", "grouped", "grouped_f64", "linear", "scalars", "herk", "trmm", "mixed", "blas12",
-                     "shard", "context"):
+    if args.only in ("split", "grouped", "grouped_f64", "grouped_kscan", "linear", "scalars", "herk", "trmm",
+                     "mixed", "blas12", "shard", "context"):
         fn = {"split": variant_split, "grouped": variant_grouped, "grouped_f64": variant_grouped_f64,
+              "grouped_kscan": variant_grouped_kscan,
               "linear": variant_linear,
               "scalars": variant_scalars, "herk": variant_herk, "trmm": variant_trmm,
               "mixed": variant_mixed, "blas12": variant_blas12, "shard": variant_shard,
