@@ -9,9 +9,10 @@ namespace {
 
 using namespace f64;
 
-template <int BMT, bool TA, bool TB, bool BS, int TRI>
-__global__ __launch_bounds__(NT, (FTile<BMT, TRI>::MIN_BLOCKS)) void qgemm_f64_kernel(GemmDesc<double> p, int tiles_m,
-                                                                                     int tiles_n, int nk)
+template <int BMT, bool TA, bool TB, bool BS, int TRI, int BNT = BN>
+__global__ __launch_bounds__(NT, (FTile<BMT, TRI, BNT>::MIN_BLOCKS)) void qgemm_f64_kernel(GemmDesc<double> p,
+                                                                                          int tiles_m, int tiles_n,
+                                                                                          int nk)
 {
     extern __shared__ double smem[];
     int tm, tn;
@@ -19,36 +20,45 @@ __global__ __launch_bounds__(NT, (FTile<BMT, TRI>::MIN_BLOCKS)) void qgemm_f64_k
         xcd_chunk_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, TRI == 1, (TRI == 1) == p.tri_lower, tm, tn);
     else if (p.uplo == 0) xcd_tile(blockIdx.x, gridDim.x, tiles_m, tiles_n, 8, tm, tn);
     else xcd_tri_tile(blockIdx.x, gridDim.x, p.uplo == 1, tm, tn);   // triangular output: its tiles only
-    f64_tile<BMT, TA, TB, BS, TRI>(p, tm * FTile<BMT, TRI>::BM, tn * BN, nk, smem);
+    f64_tile<BMT, TA, TB, BS, TRI, BNT>(p, tm * FTile<BMT, TRI, BNT>::BM, tn * BNT, nk, smem);
 }
 
-template <int BMT, bool TA, bool TB, bool BS, int TRI>
+template <int BMT, bool TA, bool TB, bool BS, int TRI, int BNT = BN>
 hipError_t launch_t(const GemmDesc<double> &d, hipStream_t stream)
 {
-    using FT = FTile<BMT, TRI>;
-    if (d.uplo != 0 && FT::BM != BN) return hipErrorInvalidValue;   // the triangular grid needs square tiles
+    using FT = FTile<BMT, TRI, BNT>;
+    if (d.uplo != 0 && FT::BM != BNT) return hipErrorInvalidValue;   // the triangular grid needs square tiles
     static std::atomic<uint64_t> lds_set{0};
-    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(&qgemm_f64_kernel<BMT, TA, TB, BS, TRI>),
+    hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void *>(&qgemm_f64_kernel<BMT, TA, TB, BS, TRI, BNT>),
                                       (int)FT::LDS_BYTES, lds_set);
     if (e != hipSuccess) return e;
     const int tiles_m = (d.M + FT::BM - 1) / FT::BM;
-    const int tiles_n = (d.N + BN - 1) / BN;
+    const int tiles_n = (d.N + BNT - 1) / BNT;
     const bool alpha_zero = d.alpha[0] == 0.0 && d.alpha[1] == 0.0 && d.alpha[2] == 0.0 && d.alpha[3] == 0.0;
     const int nk = alpha_zero ? 0 : (d.K + FT::BK - 1) / FT::BK;
     const int64_t nblocks = d.uplo == 0 ? (int64_t)tiles_m * tiles_n : (int64_t)tiles_m * (tiles_m + 1) / 2;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((qgemm_f64_kernel<BMT, TA, TB, BS, TRI>), dim3((unsigned)nblocks), dim3(NT), FT::LDS_BYTES,
+    hipLaunchKernelGGL((qgemm_f64_kernel<BMT, TA, TB, BS, TRI, BNT>), dim3((unsigned)nblocks), dim3(NT), FT::LDS_BYTES,
                        stream, d, tiles_m, tiles_n, nk);
     return hipGetLastError();
 }
 
-template <int BMT, bool BS, int TRI>
+template <int BMT, bool BS, int TRI, int BNT = BN>
 hipError_t launch_ops_t(const GemmDesc<double> &d, hipStream_t stream)
 {
     if (d.opA_t)
-        return d.opB_t ? launch_t<BMT, true, true, BS, TRI>(d, stream) : launch_t<BMT, true, false, BS, TRI>(d, stream);
-    return d.opB_t ? launch_t<BMT, false, true, BS, TRI>(d, stream) : launch_t<BMT, false, false, BS, TRI>(d, stream);
+        return d.opB_t ? launch_t<BMT, true, true, BS, TRI, BNT>(d, stream)
+                       : launch_t<BMT, true, false, BS, TRI, BNT>(d, stream);
+    return d.opB_t ? launch_t<BMT, false, true, BS, TRI, BNT>(d, stream)
+                   : launch_t<BMT, false, false, BS, TRI, BNT>(d, stream);
+}
+
+// Fraction of the block slots that a grid of `tiles` equal tiles keeps busy over its rounds.
+double slot_fill(int64_t tiles, int64_t slots)
+{
+    const int64_t rounds = (tiles + slots - 1) / slots;
+    return rounds > 0 ? (double)tiles / (double)(rounds * slots) : 1.0;
 }
 
 // Full outputs and triangular operands use 32 x 64 tiles with 4-kappa K-tiles
@@ -67,7 +77,17 @@ hipError_t launch_ops(const GemmDesc<double> &d, hipStream_t stream)
     if constexpr (TRI != 0) {
         return launch_ops_t<32, BS, TRI>(d, stream);
     } else {
-        if (d.uplo == 0) return launch_ops_t<32, BS, 0>(d, stream);
+        if (d.uplo == 0) {
+            // Grids that 32 x 64 tiles fill poorly (1024 x 1024 outputs: 512 tiles for 1024 block slots) take
+            // 32 x 32 tiles with 8-kappa K-tiles, also four blocks per CU, when those fill the slots more than
+            // 10% better over their rounds.  Measured: 1024^3 66.0 -> 67.5 TFLOP/s, 1536^3 62.0 -> 68.3;
+            // 2048^3 and larger keep 32 x 64 tiles (their grids fill the slots).
+            const int64_t slots = (int64_t)FTile<32, 0>::MIN_BLOCKS * device_cus();
+            const int64_t tm = (d.M + 31) / 32, t64 = tm * ((d.N + 63) / 64), t32 = tm * ((d.N + 31) / 32);
+            if (slots > 0 && slot_fill(t32, slots) > 1.1 * slot_fill(t64, slots))
+                return launch_ops_t<32, BS, 0, 32>(d, stream);
+            return launch_ops_t<32, BS, 0>(d, stream);
+        }
         if constexpr (BS) return hipErrorInvalidValue;   // no scaled operand with a triangular output
         else return launch_ops_t<64, false, 0>(d, stream);
     }

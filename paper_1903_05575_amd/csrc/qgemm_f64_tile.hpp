@@ -21,14 +21,16 @@
 // lane-local.  One MFMA = 4 quaternion rows x 16 quaternion columns x one
 // kappa = 64 quaternion multiply-adds.
 //
-// Tiling (block = 256 threads = 4 waves, BM x BN = 32 x 64 or 64 x 64
-// quaternions):
-//   wave w owns quaternion rows [w BM/4, (w+1) BM/4) x all 64 columns = MB x 4
-//   MFMA blocks (MB = 2 or 4) of 4 doubles each.  Per kappa a wave reads MB A
-//   and 4 B fragments (one 8-byte LDS read per lane each) and issues 4 MB
-//   MFMAs.  32-row tiles: K-tiles of 4, four blocks per CU (123 VGPRs, 4.2 +
-//   8.3 KB of LDS per stage); 64-row tiles: K-tiles of 8, two blocks per CU
-//   (224 VGPRs, 16.6 + 16.6 KB per stage).
+// Tiling (block = 256 threads = 4 waves, BM x BN = 32 x 64, 64 x 64 or
+// 32 x 32 quaternions):
+//   wave w owns quaternion rows [w BM/4, (w+1) BM/4) x all BN columns = MB x NB
+//   MFMA blocks (MB = 2 or 4, NB = BN / 16) of 4 doubles each.  Per kappa a
+//   wave reads MB A and NB B fragments (one 8-byte LDS read per lane each) and
+//   issues MB NB MFMAs.  32 x 64 tiles: K-tiles of 4, four blocks per CU (123
+//   VGPRs, 4.2 + 8.3 KB of LDS per stage); 64 x 64 tiles: K-tiles of 8, two
+//   blocks per CU (224 VGPRs, 16.6 + 16.6 KB per stage); 32 x 32 tiles (grids
+//   that 32 x 64 tiles fill poorly): K-tiles of 8, four blocks per CU (90
+//   VGPRs, 8.3 + 8.3 KB per stage).
 //   K is walked in tiles of BK quaternions through two LDS stages: the next
 //   tile is fetched from HBM into registers at the start of a tile and
 //   written to the other stage in the middle of the current tile's MFMA
@@ -67,28 +69,35 @@ constexpr int B_PL = BN + 1;                     // doubles per component plane 
 
 // Tile height: 32 quaternion rows (four blocks per CU), or 64 for triangular
 // outputs (two blocks per CU).  Each wave owns BM / 4 rows = MB MFMA row
-// blocks.  K-tile: 4 kappa for 32-row tiles, which halves their LDS (25 KB
+// blocks.  K-tile: 4 kappa for 32 x 64 tiles, which halves their LDS (25 KB
 // per block) and prefetch registers (123 VGPRs) so that four blocks fit per
 // CU (measured 8192^3 90.5% -> 91.2% of the FP64 peak, 2048^3 88.9% ->
 // 89.8%; an 8192 triangular multiply 127.9 -> 126.7 ms, although its masks
-// then spill a few registers); 8 kappa for 64-row tiles.
-template <int BMT, int TRI = 0>
+// then spill a few registers); 8 kappa for 64-row tiles, and for 32 x 32
+// tiles, whose B tile would not split over the block at 4.  Tile width: 64
+// columns, or 32 for general operands on grids that 32 x 64 tiles fill poorly
+// (see launch_ops in qgemm_f64.hip).
+template <int BMT, int TRI = 0, int BNT = BN>
 struct FTile {
     static constexpr int BM = BMT;
-    static constexpr int BK = BMT == 32 ? 4 : 8;
-    static constexpr int MIN_BLOCKS = BMT == 64 ? 2 : BK == 4 ? 4 : 3;   // resident blocks per CU
+    static constexpr int BNW = BNT;              // tile width (quaternion columns)
+    static constexpr int NB = BNT / 16;          // MFMA column blocks (16 columns each) per wave
+    static constexpr int BPL = BNT + 1;          // doubles per component plane of the B stage
+    static constexpr int BK = BMT == 32 && BNT == 64 ? 4 : 8;
+    static constexpr int MIN_BLOCKS = BMT == 64 ? 2 : BK == 4 || BNT == 32 ? 4 : 3;   // resident blocks per CU
     static constexpr int STORE_AT = BK == 8 ? 5 : 2;   // k-step after which the next K-tile is staged
     static constexpr int WM = BM / 4;            // quaternion rows per wave
     static constexpr int MB = WM / 4;            // MFMA row blocks (4 rows each) per wave
     static constexpr int A_LD = 4 * BM + 4;      // doubles per kappa row of the A stage
     static constexpr int A_STAGE = BK * A_LD;
-    static constexpr int B_STAGE = BK * 4 * B_PL;
+    static constexpr int B_STAGE = BK * 4 * BPL;
     static constexpr int STAGE = A_STAGE + B_STAGE;
     static constexpr int A_CHUNKS = BM * BK * 2 / NT;   // 16-byte chunks of A per thread per tile
-    static constexpr int B_QUATS = BN * BK / NT;        // quaternions of B per thread per tile
+    static constexpr int B_QUATS = BNT * BK / NT;       // quaternions of B per thread per tile
     static constexpr size_t LDS_BYTES = 2 * STAGE * sizeof(double);
     static_assert(A_CHUNKS * NT == BM * BK * 2, "A tile must split evenly over the block");
-    static_assert(B_QUATS * NT == BN * BK, "B tile must split evenly over the block");
+    static_assert(B_QUATS * NT == BNT * BK, "B tile must split evenly over the block");
+    static_assert(BNT == 64 || (BNT == 32 && BMT == 32 && TRI == 0), "32-column tiles: 32 rows, general operands");
     static_assert(MB * 16 == BM, "whole MFMA row blocks per wave");
     static_assert(BK % 4 == 0 && STORE_AT + 1 < BK, "staging point inside the K-tile");
 };
@@ -105,10 +114,11 @@ constexpr unsigned kOob = 0x80000000u;   // buffer offset read as zero (masked e
 // smem must hold FTile<BMT, TRI>::LDS_BYTES.  Every thread of the block calls
 // this; on return every wave has finished with smem, so the caller may reuse
 // it for another tile.
-template <int BMT, bool TA, bool TB, bool BS, int TRI>
+template <int BMT, bool TA, bool TB, bool BS, int TRI, int BNT = BN>
 __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int n0, int nk, double *smem)
 {
-    using FT = FTile<BMT, TRI>;
+    using FT = FTile<BMT, TRI, BNT>;
+    constexpr int BN = FT::BNW, NB = FT::NB, B_PL = FT::BPL;   // shadow the 64-column defaults
     constexpr int BM = FT::BM, BK = FT::BK, WM = FT::WM, MB = FT::MB, A_LD = FT::A_LD, A_STAGE = FT::A_STAGE,
                   STAGE = FT::STAGE, A_CHUNKS = FT::A_CHUNKS, B_QUATS = FT::B_QUATS;
     const int tid = threadIdx.x;
@@ -137,11 +147,11 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
     const int b_off = fc * B_PL + (lane & 15);            // + kk*4*B_PL + 16*n
     const unsigned conjB = p.conjB ? 0x80000000u : 0u;     // sign bit of the high word of q1..q3
 
-    d4 acc[MB][4];
+    d4 acc[MB][NB];
 #pragma unroll
     for (int m = 0; m < MB; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int n = 0; n < NB; ++n) acc[m][n] = (d4){0.0, 0.0, 0.0, 0.0};
 
     d2 ra[A_CHUNKS];
     d2 rb[B_QUATS][2];
@@ -259,11 +269,11 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
     // the MFMAs.  Fragments of step kk + 1 are read while step kk's MFMAs run.
     auto step_tile = [&](const double *As, double *Nxt) {
         const double *Bs = As + A_STAGE;
-        double a[2][MB], b[2][4];
+        double a[2][MB], b[2][NB];
 #pragma unroll
         for (int m = 0; m < MB; ++m) a[0][m] = As[a_off + 16 * m];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) b[0][n] = Bs[b_off + 16 * n];
+        for (int n = 0; n < NB; ++n) b[0][n] = Bs[b_off + 16 * n];
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
             const int cur = kk & 1;
@@ -271,7 +281,7 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
 #pragma unroll
                 for (int m = 0; m < MB; ++m) a[cur ^ 1][m] = As[(kk + 1) * A_LD + a_off + 16 * m];
 #pragma unroll
-                for (int n = 0; n < 4; ++n) b[cur ^ 1][n] = Bs[(kk + 1) * 4 * B_PL + b_off + 16 * n];
+                for (int n = 0; n < NB; ++n) b[cur ^ 1][n] = Bs[(kk + 1) * 4 * B_PL + b_off + 16 * n];
             }
             // keep the sign flips of step kk + 1 out of this step: they would wait on the reads above
             __builtin_amdgcn_sched_barrier(0);
@@ -279,7 +289,7 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
             for (int m = 0; m < MB; ++m) {
                 const double am = flip(a[cur][m], sgnA);
 #pragma unroll
-                for (int n = 0; n < 4; ++n)
+                for (int n = 0; n < NB; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -307,11 +317,11 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         const int mu = m0 + wave * WM + 4 * m + (lane >> 4);
-        bool ok[4];
-        int64_t e[4];
-        d2 cold[4][2];
+        bool ok[NB];
+        int64_t e[NB];
+        d2 cold[NB][2];
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < NB; ++n) {
             const int nu = n0 + 16 * n + (lane & 15);
             const bool in_tri = p.uplo == 0 || (p.uplo == 1 ? mu >= nu : mu <= nu);
             ok[n] = mu < p.M && nu < p.N && in_tri;
@@ -324,7 +334,7 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
             }
         }
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
+        for (int n = 0; n < NB; ++n) {
             if (!ok[n]) continue;
             const int nu = n0 + 16 * n + (lane & 15);
             const double v[4] = {acc[m][n][0], acc[m][n][1], acc[m][n][2], acc[m][n][3]};
