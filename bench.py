@@ -709,18 +709,20 @@ def sweep(steps, warmup):
 
 
 def probe_ops(n=2048):
-    """One launch per op pair of qgemm_d and qgemm_s, and of qgemm_mixed_d for
-    each type pair (op N/N and T/T), at M = N = K = n: a short program for
-    per-kernel counter runs (LDS bank conflicts by op pair)."""
+    """One launch per op pair of qgemm_d (at M = N = K = n and n / 2, whose
+    grid takes the 32 x 32 tiles) and qgemm_s (at n), and of qgemm_mixed_d for
+    each type pair (op N/N and T/T) at n: a short program for per-kernel
+    counter runs (LDS bank conflicts by op pair)."""
     widths = {"R": 1, "Z": 2, "Q": 4}
-    for dt, fn in ((torch.float64, q.qgemm_d), (torch.float32, q.qgemm_s)):
-        A = torch.rand(n * n * 4, dtype=dt, device="cuda")
-        B = torch.rand(n * n * 4, dtype=dt, device="cuda")
-        C = torch.zeros(n * n * 4, dtype=dt, device="cuda")
+    for dt, fn, m in ((torch.float64, q.qgemm_d, n), (torch.float64, q.qgemm_d, n // 2),
+                      (torch.float32, q.qgemm_s, n)):
+        A = torch.rand(m * m * 4, dtype=dt, device="cuda")
+        B = torch.rand(m * m * 4, dtype=dt, device="cuda")
+        C = torch.zeros(m * m * 4, dtype=dt, device="cuda")
         for oa, ob in W.OP_PAIRS:
-            fn(oa, ob, n, n, n, (1, 0, 0, 0), A, n, B, n, (0, 0, 0, 0), C, n)
+            fn(oa, ob, m, m, m, (1, 0, 0, 0), A, m, B, m, (0, 0, 0, 0), C, m)
             torch.cuda.synchronize()
-            log(f"{'qgemm_d' if dt == torch.float64 else 'qgemm_s'} {oa}/{ob} n={n}")
+            log(f"{'qgemm_d' if dt == torch.float64 else 'qgemm_s'} {oa}/{ob} n={m}")
     for ta, tb in (("Q", "R"), ("R", "Q"), ("Z", "Q"), ("Q", "Z")):
         for oa, ob in (("N", "N"), ("T", "T")):
             A = torch.rand(n * n * widths[ta], dtype=torch.float64, device="cuda")
