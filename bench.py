@@ -920,7 +920,7 @@ def main():
         "err_sample": f"{head_sample} of C from one launch of the timed kernel on the same inputs",
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64, 4),
-                     "traffic": traffic, "kernel": "qgemm_f64_kernel<32,false,false,false,0>",
+                     "traffic": traffic, "kernel": "qgemm_f64_kernel<32,false,false,false,0,64>",
                      "kernel_ms": round(ev_ms, 3)},
     }
     del A, B, C
