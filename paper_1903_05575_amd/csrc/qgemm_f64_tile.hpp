@@ -267,6 +267,14 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
     // Multiply the K-tile in stage `cur`; the registers holding the next K-tile
     // are written into stage `nxt` half way through, so those LDS writes overlap
     // the MFMAs.  Fragments of step kk + 1 are read while step kk's MFMAs run.
+    // 32-row tiles (four blocks per CU): a wave runs at raised priority except
+    // while it issues its MFMAs, so that the waves staging a K-tile, reading
+    // fragments or heading for the barrier are issued first and the MFMA pipe
+    // is fed by whichever waves are in their MFMA phase (measured: 8192^3
+    // 0.6-1.1% faster, 1024^3 1.6-1.9%, the FP64 batched launch 1.5%; the
+    // opposite priorities were slower, and so was this for 64-row tiles at two
+    // blocks per CU, 0.5-0.7%).
+    constexpr bool kPrio = BMT == 32;
     auto step_tile = [&](const double *As, double *Nxt) {
         const double *Bs = As + A_STAGE;
         double a[2][MB], b[2][NB];
@@ -284,6 +292,7 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
                 for (int n = 0; n < NB; ++n) b[cur ^ 1][n] = Bs[(kk + 1) * 4 * B_PL + b_off + 16 * n];
             }
             // keep the sign flips of step kk + 1 out of this step: they would wait on the reads above
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
@@ -293,6 +302,7 @@ __device__ __forceinline__ void f64_tile(const GemmDesc<double> &p, int m0, int 
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
             if (kk == FT::STORE_AT) store_tile(Nxt);
         }
     };
