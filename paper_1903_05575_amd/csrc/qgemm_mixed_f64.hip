@@ -242,6 +242,9 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
 #pragma unroll
                 for (int n = 0; n < NQ; ++n) b[cur ^ 1][n] = Ys[(kk + 1) * 4 * YP + y_off + 16 * n];
             }
+            // complex operand (three blocks per CU): raised wave priority outside the MFMA issue, as for the
+            // 32-row tiles of the quaternion GEMM (8192^3 125.4 -> 124.4 ms; no gain at two blocks per CU)
+            if constexpr (KC == 2) __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
@@ -251,6 +254,7 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (KC == 2) __builtin_amdgcn_s_setprio(1);
             if (kk == S::STEPS - 2) store_tile(Nxt);
         }
     };
