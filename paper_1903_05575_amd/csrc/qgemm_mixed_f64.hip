@@ -27,13 +27,13 @@
 // the result holds all four components of out(p0 + l / 16, q0 + l % 16), so
 // the alpha / beta epilogue is lane-local.
 //
-// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 128 (real
-// operand) or 32 x 64 (complex operand) quaternions of out.  Wave w owns rows
-// [8w, 8w + 8) x all BQ columns = 2 x BQ/16 MFMA blocks.  A K-tile is 4 MFMA
-// k-steps (16 kappa for a real, 8 for a complex operand), staged through two
-// LDS stages; the next K-tile is loaded at the start of a tile and written to
-// the other stage after the third k-step.  Masked elements use the out-of-range buffer offset that reads as
-// zero, so the K-loop has no branches.
+// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 64 quaternions
+// of out.  Wave w owns rows [8w, 8w + 8) x all BQ columns = 2 x BQ/16 MFMA
+// blocks.  A K-tile is 2 MFMA k-steps for a real operand and 4 for a complex
+// one (8 kappa either way), staged through two LDS stages; the next K-tile is
+// loaded at the start of a tile and written to the other stage after the
+// next-to-last k-step.  Masked elements use the out-of-range buffer offset
+// that reads as zero, so the K-loop has no branches.
 // LDS layouts (doubles):
 //   X stage: [kappa][p][4], row pitch 4 BP + 4
 //   Y stage: [kappa * KC + s][q], row pitch BQ + 1
@@ -58,20 +58,22 @@ constexpr unsigned kOob = 0x80000000u;
 // Storage type T (double or float): operands are read in T and widened
 // exactly to double while staged, so the LDS tiles, the MFMAs and the
 // epilogue arithmetic are FP64 for both; C is stored in T.
-// Tile: 32 x 128 quaternions of out (2 x 8 MFMA blocks per wave, two blocks
-// per CU) for a real operand, 32 x 64 (2 x 4 blocks, 127 VGPRs, three or more
-// blocks per CU) for a complex one; 4 MFMA k-steps per K-tile (16 kappa real,
-// 8 complex).  Measured at 8192^3: complex x quaternion 127.6 -> 123.9 ms with
-// 64 columns.  For a real operand neither 64 columns (67.6 ms against 66.3) nor
-// 64 columns with 2 k-steps at four blocks per CU (between 1% faster and 2%
-// slower depending on the host) was a clear gain, so it keeps 128 columns.
+// Tile: 32 x 64 quaternions of out (2 x 4 MFMA blocks per wave) with 2 MFMA
+// k-steps per K-tile (8 kappa) at four blocks per CU (115 VGPRs) for a real
+// operand, and with 4 k-steps (8 kappa, 127 VGPRs) at three blocks per CU for a
+// complex one.  Waves run at raised priority outside their MFMA issue (as in
+// the quaternion GEMM's 32-row tiles).  Measured at 8192^3: complex x
+// quaternion 127.6 -> 123.9 ms with 64 columns (from 128), 125.4 -> 124.4 ms
+// with the priorities; quaternion x real 66.5 -> 65.2 ms with this shape and
+// the priorities against 32 x 128 tiles at two blocks per CU (without the
+// priorities the same shape was between 1% faster and 2% slower).
 template <int KC, typename T>
 struct Shape {
-    static constexpr int BQ = KC == 2 ? 64 : 128;              // quaternion columns of out per tile
+    static constexpr int BQ = 64;              // quaternion columns of out per tile
     static constexpr int NQ = BQ / 16;                         // MFMA column blocks per wave
     static constexpr int YP = BQ + 1;                          // doubles per row of the Y stage
-    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 2;         // resident blocks per CU
-    static constexpr int STEPS = 4;                            // MFMA k-steps per K-tile
+    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 4;         // resident blocks per CU
+    static constexpr int STEPS = KC == 2 ? 4 : 2;              // MFMA k-steps per K-tile
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
@@ -242,9 +244,8 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
 #pragma unroll
                 for (int n = 0; n < NQ; ++n) b[cur ^ 1][n] = Ys[(kk + 1) * 4 * YP + y_off + 16 * n];
             }
-            // complex operand (three blocks per CU): raised wave priority outside the MFMA issue, as for the
-            // 32-row tiles of the quaternion GEMM (8192^3 125.4 -> 124.4 ms; no gain at two blocks per CU)
-            if constexpr (KC == 2) __builtin_amdgcn_s_setprio(0);
+            // raised wave priority outside the MFMA issue (see the tile comment above)
+            __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (KC == 2) __builtin_amdgcn_s_setprio(1);
+            __builtin_amdgcn_s_setprio(1);
             if (kk == S::STEPS - 2) store_tile(Nxt);
         }
     };
