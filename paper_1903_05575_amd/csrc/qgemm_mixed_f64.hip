@@ -27,12 +27,11 @@
 // the result holds all four components of out(p0 + l / 16, q0 + l % 16), so
 // the alpha / beta epilogue is lane-local.
 //
-// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 64 quaternions
-// of out.  Wave w owns rows [8w, 8w + 8) x all BQ columns = 2 x BQ/16 MFMA
-// blocks.  A K-tile is 2 MFMA k-steps for a real operand and 4 for a complex
-// one (8 kappa either way), staged through two LDS stages; the next K-tile is
-// loaded at the start of a tile and written to the other stage after the
-// next-to-last k-step.  Masked elements use the out-of-range buffer offset
+// Tiling: block = 256 threads = 4 waves, tile BP x BQ = 32 x 64 or 32 x 128
+// quaternions of out (see Shape).  Wave w owns rows [8w, 8w + 8) x all BQ
+// columns = 2 x BQ/16 MFMA blocks.  A K-tile is 2 or 4 MFMA k-steps, staged
+// through two LDS stages; the next K-tile is loaded at the start of a tile and
+// written to the other stage after the next-to-last k-step.  Masked elements use the out-of-range buffer offset
 // that reads as zero, so the K-loop has no branches.
 // LDS layouts (doubles):
 //   X stage: [kappa][p][4], row pitch 4 BP + 4
@@ -58,22 +57,32 @@ constexpr unsigned kOob = 0x80000000u;
 // Storage type T (double or float): operands are read in T and widened
 // exactly to double while staged, so the LDS tiles, the MFMAs and the
 // epilogue arithmetic are FP64 for both; C is stored in T.
-// Tile: 32 x 64 quaternions of out (2 x 4 MFMA blocks per wave) with 2 MFMA
-// k-steps per K-tile (8 kappa) at four blocks per CU (115 VGPRs) for a real
-// operand, and with 4 k-steps (8 kappa, 127 VGPRs) at three blocks per CU for a
-// complex one.  Waves run at raised priority outside their MFMA issue (as in
-// the quaternion GEMM's 32-row tiles).  Measured at 8192^3: complex x
-// quaternion 127.6 -> 123.9 ms with 64 columns (from 128), 125.4 -> 124.4 ms
-// with the priorities; quaternion x real 66.5 -> 65.2 ms with this shape and
-// the priorities against 32 x 128 tiles at two blocks per CU (without the
-// priorities the same shape was between 1% faster and 2% slower).
+// Tile: 32 x 64 quaternions of out (2 x 4 MFMA blocks per wave) for a complex
+// operand (4 MFMA k-steps = 8 kappa per K-tile, 127 VGPRs, three blocks per
+// CU) and for a real operand in float storage (2 k-steps = 8 kappa, 115 VGPRs,
+// four blocks per CU); 32 x 128 (2 x 8 blocks, 4 k-steps = 16 kappa, two
+// blocks per CU) for a real operand in double storage.  At three or more
+// blocks per CU the waves run at raised priority outside their MFMA issue (as
+// in the quaternion GEMM's 32-row tiles).  Measured at 8192^3 (interleaved
+// runs on one host): complex x quaternion 127.6 -> 123.9 ms with 64 columns
+// (from 128) and 125.4 -> 124.4 ms with the priorities; quaternion x real in
+// float storage 65.9 -> 64.5 ms on the 32 x 64 shape with the priorities (66.4
+// -> 65.0 on another host), but in double storage that shape was 2% faster on
+// one host and 4% slower on another (66.0 against 68.8 ms), so double storage
+// keeps the wide tile.
 template <int KC, typename T>
 struct Shape {
-    static constexpr int BQ = 64;              // quaternion columns of out per tile
+    // a real operand in double storage keeps the 32 x 128 tile at two blocks per CU; a real operand in float
+    // storage and a complex one take 32 x 64 tiles at four and three blocks per CU
+    static constexpr bool WIDE = KC == 1 && sizeof(T) == 8;
+    static constexpr int BQ = WIDE ? 128 : 64;                 // quaternion columns of out per tile
     static constexpr int NQ = BQ / 16;                         // MFMA column blocks per wave
-    static constexpr int YP = BQ + 1;                          // doubles per row of the Y stage
-    static constexpr int MIN_BLOCKS = KC == 2 ? 3 : 4;         // resident blocks per CU
-    static constexpr int STEPS = KC == 2 ? 4 : 2;              // MFMA k-steps per K-tile
+    static constexpr int MIN_BLOCKS = WIDE ? 2 : KC == 2 ? 3 : 4;   // resident blocks per CU
+    static constexpr int STEPS = KC == 1 && !WIDE ? 2 : 4;     // MFMA k-steps per K-tile
+    static constexpr bool PRIO = MIN_BLOCKS >= 3;              // raised wave priority outside the MFMA issue
+    // doubles per row of the Y stage: with 8-kappa K-tiles of a real operand the 16 lanes of a store group
+    // write 8 kappa x 2 columns, which a pitch of 2 (mod 32 doubles) spreads over distinct banks
+    static constexpr int YP = BQ + (KC == 1 && !WIDE ? 2 : 1);
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
@@ -245,7 +254,7 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
                 for (int n = 0; n < NQ; ++n) b[cur ^ 1][n] = Ys[(kk + 1) * 4 * YP + y_off + 16 * n];
             }
             // raised wave priority outside the MFMA issue (see the tile comment above)
-            __builtin_amdgcn_s_setprio(0);
+            if constexpr (S::PRIO) __builtin_amdgcn_s_setprio(0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(NT, (Shape<KC, T>::MIN_BLOCKS)) void qgemm_mixed_f6
                     acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, b[cur][n], acc[m][n], 0, 0, 0);
             }
             __builtin_amdgcn_sched_barrier(0);
-            __builtin_amdgcn_s_setprio(1);
+            if constexpr (S::PRIO) __builtin_amdgcn_s_setprio(1);
             if (kk == S::STEPS - 2) store_tile(Nxt);
         }
     };
