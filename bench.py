@@ -710,9 +710,10 @@ def sweep(steps, warmup):
 
 def probe_ops(n=2048):
     """One launch per op pair of qgemm_d (at M = N = K = n and n / 2, whose
-    grid takes the 32 x 32 tiles) and qgemm_s (at n), and of qgemm_mixed_d for
-    each type pair (op N/N and T/T) at n: a short program for per-kernel
-    counter runs (LDS bank conflicts by op pair)."""
+    grid takes the 32 x 32 tiles) and qgemm_s (at n), of qgemm_mixed_d for each
+    type pair (op N/N and T/T) at n, and of qgemm_mixed_s for the real type
+    pairs: a short program for per-kernel counter runs (LDS bank conflicts by
+    op pair)."""
     widths = {"R": 1, "Z": 2, "Q": 4}
     for dt, fn, m in ((torch.float64, q.qgemm_d, n), (torch.float64, q.qgemm_d, n // 2),
                       (torch.float32, q.qgemm_s, n)):
@@ -731,6 +732,15 @@ def probe_ops(n=2048):
             q.qgemm_mixed(ta, tb, oa, ob, n, n, n, (1, 0, 0, 0), A, n, B, n, (0, 0, 0, 0), C, n)
             torch.cuda.synchronize()
             log(f"qgemm_mixed {ta}x{tb} {oa}/{ob} n={n}")
+    # float storage: a real operand takes the 32 x 64 tiles with 8-kappa K-tiles there
+    for ta, tb in (("Q", "R"), ("R", "Q")):
+        for oa, ob in (("N", "N"), ("T", "T")):
+            A = torch.rand(n * n * widths[ta], dtype=torch.float32, device="cuda")
+            B = torch.rand(n * n * widths[tb], dtype=torch.float32, device="cuda")
+            C = torch.zeros(n * n * 4, dtype=torch.float32, device="cuda")
+            q.qgemm_mixed(ta, tb, oa, ob, n, n, n, (1, 0, 0, 0), A, n, B, n, (0, 0, 0, 0), C, n)
+            torch.cuda.synchronize()
+            log(f"qgemm_mixed_s {ta}x{tb} {oa}/{ob} n={n}")
 
 
 def smi_reading():
