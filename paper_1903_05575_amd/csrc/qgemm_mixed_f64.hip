@@ -80,9 +80,7 @@ struct Shape {
     static constexpr int MIN_BLOCKS = WIDE ? 2 : KC == 2 ? 3 : 4;   // resident blocks per CU
     static constexpr int STEPS = KC == 1 && !WIDE ? 2 : 4;     // MFMA k-steps per K-tile
     static constexpr bool PRIO = MIN_BLOCKS >= 3;              // raised wave priority outside the MFMA issue
-    // doubles per row of the Y stage: with 8-kappa K-tiles of a real operand the 16 lanes of a store group
-    // write 8 kappa x 2 columns, which a pitch of 2 (mod 32 doubles) spreads over distinct banks
-    static constexpr int YP = BQ + (KC == 1 && !WIDE ? 2 : 1);
+    static constexpr int YP = BQ + 1;                          // doubles per row of the Y stage
     static constexpr int BK = STEPS * 4 / KC;                  // kappa per K-tile
     static constexpr int X_STAGE = BK * XP;
     static constexpr int Y_STAGE = BK * KC * YP;
