@@ -171,3 +171,16 @@ def test_ops_ragged_full_output_tiles(gpu, opA, opB):
         want = oracle.qgemm(opA, opB, M, N, K, p["alpha"], p["A"], p["lda"], p["B"], p["ldb"], p["beta"], p["C"],
                             p["ldc"])
         check(p, host(Cd), want, f"32-row tiles {opA}{opB} {M}x{N}x{K}")
+
+
+@pytest.mark.parametrize("opA", "NTCR")
+@pytest.mark.parametrize("opB", "NTCR")
+def test_tile_width_choice_both_sides(gpu, opA, opB):
+    """Full outputs whose 32 x 64 grid fills the block slots poorly take 32 x 32
+    tiles with 8-kappa K-tiles (1000 x 1000: 32 x 16 = 512 tiles against 1024
+    of 32 x 32); 1100 x 1100 keeps the 32 x 64 tiles (630 of them, no better
+    filled by 32 x 32).  Both ragged in M, N and K, padded leading dimensions,
+    every op pair: within the bar on every element."""
+    for i, (M, N, K) in enumerate(((1000, 1000, 37), (1100, 1100, 29))):
+        p = W.gemm_problem(1700 + 32 * i + "NTCR".index(opA) * 4 + "NTCR".index(opB), M, N, K, opA, opB, pad=1)
+        check(p, run_gpu(p), run_oracle(p), f"tile width {opA}{opB} {M}x{N}x{K}")
