@@ -127,3 +127,14 @@ def test_mixed_f32_quaternion_pair_is_qgemm_s(gpu):
     q.qgemm_mixed("Q", "Q", "N", "C", 100, 90, 80, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], Cm, p["ldc"])
     q.qgemm_s("N", "C", 100, 90, 80, p["alpha"], A, p["lda"], B, p["ldb"], p["beta"], Cg, p["ldc"])
     np.testing.assert_array_equal(host(Cm), host(Cg))
+
+
+@pytest.mark.parametrize("tA,tB", PAIRS)
+@pytest.mark.parametrize("opA,opB", [("N", "N"), ("T", "T")])
+def test_mixed_f32_many_tiles(gpu, tA, tB, opA, opB):
+    """Float storage, several tiles in both directions and many K-tiles (a real
+    operand takes 32 x 64 tiles with 8-kappa K-tiles here), ragged everywhere."""
+    p = as32(W.mixed_problem(1240 + PAIRS.index((tA, tB)) * 2 + (opA == "T"), tA, tB, 333, 290, 517, opA, opB,
+                             dist="normal", pad=3))
+    got = check(p, 1e-7)
+    assert got.dtype == np.float32
